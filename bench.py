@@ -1,0 +1,231 @@
+"""Throughput of the multi-start UBQP hot path on one MI355X.
+
+A step is one generation of the multi-start loop over M candidates:
+diversify -> exact evaluation -> T(lambda) screening -> steepest ascent of the
+passers -> incumbent update and next seeds, all on the device through the C ABI.
+
+Workload (the configuration the headline metric is quoted on): n = 7000
+variables, 50% density, coefficients uniform in [-100, 100] \\ {0}, M = 16384
+candidates per generation (S = 820 seeds x 10 Glover steps x {x', x''}),
+lambda = 1/2, ascent to a 1-flip local optimum.  Synthetic seeded instance
+(stand-in for the Palubeckis n = 7000 problems).
+
+value = candidates evaluated and processed per second over the timed
+generations (whole path).  Also reported: the batched evaluation alone, the
+paper's Table 1 replica (1000 random solutions, n = 2500..7000), the roofline
+of the dominant kernel from stream events recorded around each phase during the
+timed generations, and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "exact xQx evals/s at n=7000 (vs plain); served solves/s + p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0      # dense int8 matrix-core peak, TOP/s
+VALU_INT32_TOPS = 39.3       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, int32 ops/s / 1e12
+PAPER_TABLE1_S = {2500: 0.7, 5000: 2.0, 6000: 3.0, 7000: 3.5}   # GPU seconds per 1000 evals
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-e1", action="store_true")
+    ap.add_argument("--lam", default="1/2")
+    return ap.parse_args()
+
+
+def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
+    """The oracle as it stands, on the host cores, timed on a bounded sample of the
+    workload.  Measured: the objective of 32*threads candidates (threads in
+    parallel), one closed-form delta vector (the ascent's initialisation) and
+    `threads` full ascents from random candidates (threads in parallel).  A
+    generation then costs (M t_eval + P t_init + F t_flip) / threads of wall time
+    with the timed generations' own passer count P and flip count F."""
+    import oracle
+    from paper_1706_00037_amd.inputs import random_candidates
+
+    Ne = 32 * threads
+    Xs = random_candidates(Ne, n, 99)
+    t = time.perf_counter()
+    oracle.eval_many(Q, Xs, threads=threads)
+    t_eval = (time.perf_counter() - t) * threads / Ne            # serial seconds per candidate
+    t = time.perf_counter()
+    oracle.delta(Q, Xs[0])
+    t_init = time.perf_counter() - t                              # serial seconds per initialisation
+    Xa = random_candidates(threads, n, 98)
+    fa = oracle.eval_many(Q, Xa, threads=threads)
+    t = time.perf_counter()
+    _, _, fl = oracle.ascent_many(Q, Xa, np.arange(threads, dtype=np.int32), fa, threads=threads)
+    t_asc = time.perf_counter() - t
+    F = float(fl.sum())
+    t_flip = max(0.0, t_asc * threads - threads * t_init) / max(F, 1.0)
+    t_gen = (M * t_eval + P_per_gen * t_init + flips_per_gen * t_flip) / threads
+    return dict(value=M / t_gen, unit="evals/s", cores=threads, kind="oracle",
+                sample=f"oracle at n={n}: objective of {Ne} candidates, one delta initialisation and {threads} "
+                       f"ascents from random candidates ({int(F)} flips), on {threads} threads; generation time "
+                       f"(M t_eval + P t_init + F t_flip)/threads with the timed generations' mean "
+                       f"P={P_per_gen:.0f}, F={flips_per_gen:.0f}",
+                ms_per_step=t_gen * 1e3, eval_only_evals_per_s=threads / t_eval,
+                t_eval_ms=t_eval * 1e3, t_init_ms=t_init * 1e3, t_flip_us=t_flip * 1e6)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1706_00037_amd import ubqp
+    from paper_1706_00037_amd.inputs import CONFIGS, make_instance, random_candidates
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    c = CONFIGS["cfg3"]
+    n, M, H = c["n"], c["M"], c["H"]
+    lam_num, lam_den = (int(t) for t in args.lam.split("/"))
+    K, Wm = args.steps, args.warmup
+    log(f"[bench] instance n={n} density={c['density']} seed={c['inst_seed']}")
+    Q = make_instance(n, c["density"], c["lo"], c["hi"], c["inst_seed"])
+    ctx = ubqp.Context(0)
+    prob = ctx.problem(Q)
+
+    # ---- whole-path generations ------------------------------------------------
+    G = Wm + K
+    run = ctx.run(prob, M=M, H=H, lam_num=lam_num, lam_den=lam_den, G=G, run_seed=c["run_seed"],
+                  flags=ubqp.UBQP_TIMING)
+    log(f"[bench] warmup {Wm} generations")
+    run.step(Wm)
+    run.result()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {K} generations")
+    t0 = time.perf_counter()
+    run.step(K)
+    res = run.result()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run.close()
+    wall_ms = (t1 - t0) * 1e3 / K
+    gen_ms = np.diff(np.concatenate([[res["gen_ms"][Wm - 1] if Wm > 0 else 0.0], res["gen_ms"][Wm:]]))
+    ph = res["phase_ms"][Wm:]
+    st = res["stats"][Wm:]
+    phase_mean = {name: float(ph[:, i].mean()) for i, name in enumerate(ubqp.PHASES)}
+    P_mean, flips_mean = float(st[:, 2].mean()), float(st[:, 3].mean())
+    log(f"[bench] {wall_ms:.3f} ms/generation; phases {phase_mean}; P={P_mean:.0f} flips={flips_mean:.0f}")
+
+    # ---- evaluation alone (the batched exact objective) ------------------------
+    X = random_candidates(M, n, 5)
+    Xd = torch.from_numpy(X.view(np.int64)).cuda()
+    fd = torch.empty(M, dtype=torch.int64, device="cuda")
+    for _ in range(3):
+        ctx.eval(prob, Xd, fd)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    R = 20
+    e0.record(stream)
+    for _ in range(R):
+        ctx.eval(prob, Xd, fd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eval_ms = e0.elapsed_time(e1) / R
+    n_pad = prob.n_pad
+    useful_ops = 2.0 * M * n * n
+    exec_ops = 2.0 * M * n_pad * n_pad
+    log(f"[bench] eval alone {eval_ms:.3f} ms: {useful_ops / eval_ms / 1e9:.1f} TOP/s useful")
+
+    # ---- roofline of the dominant phase ------------------------------------------
+    dom = max(phase_mean, key=phase_mean.get)
+    if dom == "eval":
+        t_ms = phase_mean["eval"]
+        ach = useful_ops / (t_ms * 1e-3) / 1e12
+        roof = dict(kernel="eval_kernel (int8 MFMA Y = XQ, fused row dot)", bound="mfma", achieved=ach,
+                    peak=INT8_PEAK_TOPS, unit="TFLOP/s", frac=ach / INT8_PEAK_TOPS, traffic=None,
+                    algorithmic="2 n^2 int8 ops per candidate x M candidates per launch",
+                    avg_launch_ms=t_ms)
+    else:
+        t_ms = phase_mean[dom]
+        # ascent: per flip, n int8 entries read and ~5.5 int32 VALU ops per variable
+        ops = flips_mean * n * 5.5
+        ach = ops / (t_ms * 1e-3) / 1e12
+        roof = dict(kernel=f"{dom} phase", bound="alu", achieved=ach, peak=VALU_INT32_TOPS, unit="TOP/s",
+                    frac=ach / VALU_INT32_TOPS, traffic=None,
+                    algorithmic="5.5 int32 VALU ops per variable per flip", avg_launch_ms=t_ms)
+
+    # ---- the paper's Table 1 replica: 1000 random solutions --------------------------
+    e1_rep = {}
+    if not args.no_e1:
+        for nn, dens, seed in ((2500, 0.1, 6001), (5000, 0.5, 6002), (6000, 0.5, 6003), (7000, 0.5, 6004)):
+            Qe = Q if nn == n else make_instance(nn, dens, -100, 100, seed)
+            pe = prob if nn == n else ctx.problem(Qe)
+            Xe = torch.from_numpy(random_candidates(1000, nn, seed).view(np.int64)).cuda()
+            fe = torch.empty(1000, dtype=torch.int64, device="cuda")
+            ctx.eval(pe, Xe, fe)
+            e0.record(stream)
+            for _ in range(10):
+                ctx.eval(pe, Xe, fe)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 10
+            e1_rep[str(nn)] = dict(ms_per_1000=ms, paper_gpu_s=PAPER_TABLE1_S[nn],
+                                   speedup_vs_paper_gpu=PAPER_TABLE1_S[nn] * 1e3 / ms)
+            log(f"[bench] 1000 evals n={nn}: {ms:.3f} ms (paper GTX 780 Ti: {PAPER_TABLE1_S[nn]} s)")
+
+    # ---- CPU oracle -----------------------------------------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"[bench] cpu baseline with {threads} threads")
+        cpu = cpu_baseline(Q, n, M, P_mean, flips_mean, threads)
+
+    out = {
+        "metric": METRIC,
+        "value": M * K / (t1 - t0),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": wall_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": f"n={n}, density {c['density']}, coefficients in [-100,100], M={M} candidates "
+                               f"per generation (H={H}), lambda={lam_num}/{lam_den}, ascent to a local optimum; "
+                               f"one step = one generation (diversify, eval, screen, ascent, select)",
+                   "n": n, "M": M, "H": H, "lambda": f"{lam_num}/{lam_den}", "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "phases_ms": phase_mean,
+        "gen_ms_events": float(gen_ms.mean()),
+        "passers_per_gen": P_mean,
+        "flips_per_gen": flips_mean,
+        "eval_only": {"ms": eval_ms, "evals_per_s": M / (eval_ms * 1e-3),
+                      "useful_tops": useful_ops / eval_ms / 1e9, "executed_tops": exec_ops / eval_ms / 1e9,
+                      "frac_int8_peak": useful_ops / eval_ms / 1e9 / INT8_PEAK_TOPS},
+        "e1_replica": e1_rep,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

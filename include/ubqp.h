@@ -1,0 +1,203 @@
+/*
+ * ubqp.h -- C ABI of libubqp.so, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of the diversified multi-start method for the
+ * Unconstrained Binary Quadratic Problem (Lewis, arXiv:1706.00037):
+ *
+ *     maximise f(x) = x^T Q x,  Q symmetric integer n x n,  x in {0,1}^n
+ *                                                   (problem (P), Introduction)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers with suffix _d are device memory owned by the caller; the library
+ *   never frees them.  Pointers with suffix _host are host memory.
+ * - Solutions are bit-packed: W = ceil(n/64) uint64 words per solution, bit j in
+ *   word j/64 at position j%64.  Bits at positions >= n must be 0 on input and
+ *   are 0 on output.  A population of M solutions is M consecutive rows.
+ * - Objective values are int64; everything on the path is exact integer
+ *   arithmetic.  Coefficients must lie in [-32768, 32767] and n in [1, 8192]
+ *   (the int32 accumulators of the int8 matrix-core contraction are exact in
+ *   that range).
+ * - Calls are asynchronous on the context's stream unless stated otherwise;
+ *   device outputs are valid after the stream has been synchronised.
+ * - Every call returns UBQP_OK (0) or a negative error code; no exception
+ *   crosses the ABI.  ubqp_last_error() gives a message for the last failure
+ *   on a context.  A context must not be used from two threads at once.
+ */
+#ifndef UBQP_H
+#define UBQP_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define UBQP_API __attribute__((visibility("default")))
+#else
+#define UBQP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UBQP_OK 0
+#define UBQP_EINVAL -1  /* null pointer, size or parameter out of its domain        */
+#define UBQP_ERANGE -2  /* coefficient or n beyond the exactness bounds above       */
+#define UBQP_EASYM -3   /* Q is not symmetric                                       */
+#define UBQP_ENOMEM -4  /* device allocation failed                                 */
+#define UBQP_EDEVICE -5 /* a HIP call or a kernel-side check failed (see last_error) */
+
+#define UBQP_MAX_N 8192
+#define UBQP_MAX_M (1ll << 22)
+#define UBQP_MAX_H 256
+
+/* flags of ubqp_params */
+#define UBQP_DERIV_START 1u /* generation-0 seed 0 is the first-derivative solution */
+#define UBQP_TIMING 2u      /* record stream events around every phase of a generation */
+
+/* phases of a generation, in order (ubqp_result.phase_ms_host) */
+#define UBQP_PHASE_DIVERSIFY 0
+#define UBQP_PHASE_EVAL 1
+#define UBQP_PHASE_SCREEN 2
+#define UBQP_PHASE_ASCENT 3 /* Delta initialisation and ascent of all passers */
+#define UBQP_PHASE_SELECT 4
+#define UBQP_PHASES 5
+
+typedef struct ubqp_ctx ubqp_ctx;         /* library-owned: device, stream, workspace */
+typedef struct ubqp_problem ubqp_problem; /* library-owned: Q resident on the device  */
+
+/* Parameters of the multi-start loop (Fig. 2 of the paper, run one generation of
+ * M candidates at a time). */
+typedef struct {
+    int64_t M;          /* candidates per generation, 1..UBQP_MAX_M                    */
+    int32_t H;          /* diversification steps h = 1..H per seed (x' and x'' each);  */
+                        /* S = ceil(M / 2H) seeds per generation                       */
+    int32_t lam_num;    /* screening lambda = lam_num / lam_den, 0 <= lambda <= 1      */
+    int32_t lam_den;
+    int32_t G;          /* generations (iterations of the main loop), >= 1             */
+    int32_t max_flips;  /* flips per ascent, 0 = until a 1-flip local optimum          */
+    uint32_t flags;     /* UBQP_DERIV_START | UBQP_TIMING                              */
+    uint64_t run_seed;  /* SplitMix64 seed of the random solutions                     */
+} ubqp_params;
+
+/* Result of a multi-start run.  Buffers are caller-owned; any may be NULL. */
+typedef struct {
+    int64_t best_f;         /* out: incumbent value (INT64_MIN if no candidate ever passed) */
+    int32_t have_best;      /* out: 1 if an incumbent exists                               */
+    int32_t generations;    /* out: generations completed so far                           */
+    uint64_t *best_x_host;  /* out, W words: incumbent solution                            */
+    int64_t *stats_host;    /* out, G x 5: per generation {Sum, Max, passers, flips,       */
+                            /*   incumbent after the generation}                           */
+    double *gen_ms_host;    /* out, G: milliseconds from the start of the run to the end   */
+                            /*   of each generation, measured with stream events           */
+    double *phase_ms_host;  /* out, G x UBQP_PHASES: milliseconds of each phase (runs      */
+                            /*   created with UBQP_TIMING; left untouched otherwise)       */
+} ubqp_result;
+
+typedef struct ubqp_run ubqp_run;  /* library-owned: the device state of one multi-start run */
+
+/* Create a context on HIP device `device` that launches on `stream` (a
+ * hipStream_t; 0 is the null stream).  *out receives the handle. */
+UBQP_API int ubqp_create(ubqp_ctx **out, int device, void *stream);
+/* Change the stream later calls launch on. */
+UBQP_API int ubqp_set_stream(ubqp_ctx *ctx, void *stream);
+/* Release the context and its workspace.  Problems created on it must be destroyed first. */
+UBQP_API int ubqp_destroy(ubqp_ctx *ctx);
+/* Message describing the last error on ctx (never NULL; "" if none). */
+UBQP_API const char *ubqp_last_error(const ubqp_ctx *ctx);
+/* Block until all work issued on the context's stream has completed. */
+UBQP_API int ubqp_sync(ubqp_ctx *ctx);
+
+/*
+ * Upload Q once and keep it resident (the paper copies Q to the GPU a single
+ * time, Pseudocode section).  q_host: n x n int32, row-major, must be symmetric
+ * with every entry in [-32768, 32767].  Entries all in [-128, 127] are stored
+ * as one int8 plane; otherwise as two int8 planes hi = q >> 8 and
+ * lo = (q & 255) - 128, so that q = 256 hi + lo + 128 exactly.  Synchronous.
+ * Errors: UBQP_EINVAL (n out of [1, UBQP_MAX_N], null), UBQP_ERANGE, UBQP_EASYM,
+ * UBQP_ENOMEM.
+ */
+UBQP_API int ubqp_problem_create(ubqp_ctx *ctx, int32_t n, const int32_t *q_host, ubqp_problem **out);
+UBQP_API int ubqp_problem_destroy(ubqp_problem *prob);
+/* n, padded size n_pad (a multiple of 128) and number of int8 planes (1 or 2). */
+UBQP_API int ubqp_problem_info(const ubqp_problem *prob, int32_t *n, int32_t *n_pad, int32_t *planes);
+
+/*
+ * Glover diversification (Pseudocode section, "Diversify"; Glover 1998):
+ * candidate c (0 <= c < M) is built from seed s = c / (2H) with step
+ * h = (c mod 2H)/2 + 1: the seed with variables j = 0, h, 2h, ... flipped (x')
+ * when c is even, the complement of x' (x'') when c is odd.
+ * seeds_d: S x W, X_d: M x W (output).  Requires 1 <= H <= UBQP_MAX_H and
+ * M <= 2 H S.
+ */
+UBQP_API int ubqp_diversify(ubqp_ctx *ctx, int32_t n, const uint64_t *seeds_d, int64_t S, int32_t H,
+                   uint64_t *X_d, int64_t M);
+
+/*
+ * Exact objective of M candidates (Introduction, problem (P); the evaluation
+ * the paper moves to the GPU): f_d[c] = X_c^T Q X_c.  X_d: M x W, f_d: M int64
+ * (output).  Computed as Y = X Q on int8 matrix cores with int32 accumulation,
+ * fused with the row dot product sum_j x_j Y_j in int64.
+ */
+UBQP_API int ubqp_eval(ubqp_ctx *ctx, const ubqp_problem *prob, const uint64_t *X_d, int64_t M,
+              int64_t *f_d);
+
+/*
+ * Screening (Pseudocode section): T(lambda) = Mean + lambda (Max - Mean) over
+ * the M values f_d, lambda = lam_num / lam_den; candidate c passes iff
+ * f_d[c] > T, decided exactly as
+ *     lam_den * M * f  >  (lam_den - lam_num) * Sum + lam_num * M * Max.
+ * Outputs: pass_idx_d (M int32 capacity) gets the passer indices in ascending
+ * order, n_pass_d (1 int64) their count, sum_max_d (2 int64) {Sum, Max}.
+ */
+UBQP_API int ubqp_screen(ubqp_ctx *ctx, const int64_t *f_d, int64_t M, int32_t lam_num, int32_t lam_den,
+                int32_t *pass_idx_d, int64_t *n_pass_d, int64_t *sum_max_d);
+
+/*
+ * Steepest 1-flip ascent (Pseudocode section; deltas of Glover et al. 2002) of
+ * the candidates X_d[idx_d[p]], p < *n_idx_d (device count, at most max_idx);
+ * X_d, f_d and flips_d have M rows:
+ * repeatedly flip the variable with the largest
+ *     Delta_i = (1 - 2 x_i) (q_ii + 2 sum_{j != i} q_ij x_j),
+ * the lowest index among equal maxima, while that Delta is > 0 and fewer than
+ * max_flips flips were made (max_flips == 0: no cap).  In place: rows of X_d,
+ * f_d[c] (in: f of the row, out: f after ascent) and flips_d[c] (int32, out).
+ * Rows not listed are untouched.  Listed indices outside [0, M) are skipped.
+ * Both that and an uncapped ascent exceeding the library's safety bound of
+ * 64 n_pad + 4096 flips are reported as UBQP_EDEVICE by the next ubqp_sync
+ * (or ubqp_multistart).
+ */
+UBQP_API int ubqp_ascent(ubqp_ctx *ctx, const ubqp_problem *prob, uint64_t *X_d, int64_t M, const int32_t *idx_d,
+                const int64_t *n_idx_d, int64_t max_idx, int64_t *f_d, int32_t max_flips,
+                int32_t *flips_d);
+
+/*
+ * The multi-start loop (Fig. 2), one generation of M candidates at a time, on
+ * the device with no host synchronisation inside a generation:
+ *   seeds -> diversify -> evaluate -> screen -> ascent of the passers ->
+ *   incumbent update (strict '>', earliest index wins) -> next seeds.
+ * Generation-0 seeds are random: word w of seed s in generation g is output
+ * (g S + s) W + w of SplitMix64 seeded with run_seed, bits >= n cleared
+ * (seed 0 is the derivative start with UBQP_DERIV_START).  Next generation:
+ * seed 0 = incumbent, then the ascended passers by (f desc, index asc), then
+ * random solutions.
+ *
+ * ubqp_run_create allocates the run's device state (ubqp_run_footprint bytes)
+ * and queues the generation-0 seeds; ubqp_run_step queues `generations` more
+ * generations (at most params->G in total) and returns without waiting;
+ * ubqp_run_result waits for them and fills *result.  f_dump_d (optional,
+ * device, G x M int64) receives every candidate's f before ascent.
+ */
+UBQP_API int64_t ubqp_run_footprint(const ubqp_problem *prob, const ubqp_params *params);
+UBQP_API int ubqp_run_create(ubqp_ctx *ctx, const ubqp_problem *prob, const ubqp_params *params,
+                             int64_t *f_dump_d, ubqp_run **out);
+UBQP_API int ubqp_run_step(ubqp_run *run, int32_t generations);
+UBQP_API int ubqp_run_result(ubqp_run *run, ubqp_result *result);
+UBQP_API int ubqp_run_destroy(ubqp_run *run);
+
+/* The whole loop in one synchronous call: create, params->G steps, result, destroy. */
+UBQP_API int ubqp_multistart(ubqp_ctx *ctx, const ubqp_problem *prob, const ubqp_params *params,
+                             int64_t *f_dump_d, ubqp_result *result);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UBQP_H */

@@ -1,0 +1,315 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every comparison is bit-exact: all arithmetic on the path is integer.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1706_00037_amd.inputs import CONFIGS, make_instance, random_candidates, unpack_bits
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1706_00037_amd import ubqp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ubqp.Context(0)
+
+
+def dev(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(a).cuda()
+
+
+def host_u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+# ----------------------------------------------------------------- eval ----
+
+EVAL_CASES = [
+    # n, M, density, lo, hi
+    (1, 1, 1.0, -100, 100),
+    (2, 5, 1.0, -100, 100),
+    (63, 300, 0.5, -128, 127),
+    (64, 257, 0.5, -128, 127),
+    (65, 511, 0.5, -128, 127),
+    (127, 256, 0.3, -100, 100),
+    (128, 255, 0.3, -100, 100),
+    (129, 1000, 0.3, -100, 100),
+    (500, 1000, 0.1, -100, 100),
+    (1000, 777, 0.5, -100, 100),
+    (2500, 600, 0.1, -100, 100),
+    (129, 300, 0.5, -32768, 32767),
+    (700, 513, 1.0, -32768, 32767),
+    (1000, 300, 0.3, -300, 300),
+]
+
+
+@pytest.mark.parametrize("n,M,d,lo,hi", EVAL_CASES)
+def test_eval_matches_oracle(ctx, n, M, d, lo, hi):
+    Q = make_instance(n, d, lo, hi, 1000 + n + M)
+    X = random_candidates(M, n, 2000 + n)
+    X[0] = 0                                              # all-zero candidate
+    if M > 1:
+        X[1] = random_candidates(1, n, 1, p_one=1.0)[0]   # all-one candidate
+    prob = ctx.problem(Q)
+    assert prob.planes == (1 if -128 <= lo and hi <= 127 else 2)
+    fd = torch.full((M,), 12345, dtype=torch.int64, device="cuda")
+    ctx.eval(prob, dev(X), fd)
+    torch.cuda.synchronize()
+    assert np.array_equal(fd.cpu().numpy(), oracle.eval_many(Q, X, threads=8))
+
+
+@pytest.mark.parametrize("n,v", [(7000, 127), (7000, -128), (2000, 32767), (2000, -32768), (4113, 127)])
+def test_eval_extremes_beyond_int32(ctx, n, v):
+    """Constant Q: f(1) = v n^2 exceeds int32; f(0) = 0; f(e_0) = v."""
+    Q = np.full((n, n), v, np.int32)
+    W = (n + 63) // 64
+    X = np.zeros((3, W), np.uint64)
+    X[0] = random_candidates(1, n, 1, p_one=1.0)[0]
+    X[2, 0] = 1
+    prob = ctx.problem(Q)
+    fd = torch.empty(3, dtype=torch.int64, device="cuda")
+    ctx.eval(prob, dev(X), fd)
+    torch.cuda.synchronize()
+    assert list(fd.cpu().numpy()) == [v * n * n, 0, v]
+
+
+def test_eval_full_size_sampled(ctx):
+    """7000 variables, 50% density, 16384 candidates: sampled rows against the oracle."""
+    c = CONFIGS["cfg3"]
+    n, M = c["n"], c["M"]
+    Q = make_instance(n, c["density"], c["lo"], c["hi"], c["inst_seed"])
+    X = random_candidates(M, n, 31)
+    prob = ctx.problem(Q)
+    fd = torch.empty(M, dtype=torch.int64, device="cuda")
+    ctx.eval(prob, dev(X), fd)
+    torch.cuda.synchronize()
+    f = fd.cpu().numpy()
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([[0, 1, M - 1, 255, 256, 8191, 8192], rng.choice(M, 25, replace=False)])
+    want = oracle.eval_many(Q, X[rows], threads=8)
+    assert np.array_equal(f[rows], want)
+
+
+# ------------------------------------------------------------ diversify ----
+
+@pytest.mark.parametrize("n,S,H,M", [(1, 3, 10, 55), (5, 2, 3, 12), (64, 7, 10, 133), (65, 7, 10, 140),
+                                     (500, 50, 10, 1000), (300, 4, 200, 1500), (7000, 820, 10, 16384)])
+def test_diversify_matches_oracle(ctx, n, S, H, M):
+    seeds = random_candidates(S, n, 40 + n)
+    Xd = torch.full((M, (n + 63) // 64), -1, dtype=torch.int64, device="cuda")
+    ctx.diversify(n, dev(seeds), H, Xd)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u64(Xd), oracle.diversify(n, seeds, H, M))
+
+
+# --------------------------------------------------------------- screen ----
+
+def _screen(ctx, f, p, q):
+    M = f.shape[0]
+    idx = torch.full((M,), -7, dtype=torch.int32, device="cuda")
+    npass = torch.empty(1, dtype=torch.int64, device="cuda")
+    sm = torch.empty(2, dtype=torch.int64, device="cuda")
+    ctx.screen(dev(f), p, q, idx, npass, sm)
+    torch.cuda.synchronize()
+    P = int(npass.item())
+    return idx.cpu().numpy()[:P], int(sm[0].item()), int(sm[1].item())
+
+
+@pytest.mark.parametrize("M", [1, 2, 100, 2047, 2048, 2049, 65536, 100003])
+@pytest.mark.parametrize("lam", [(0, 1), (3, 10), (1, 2), (4, 5), (1, 1)])
+def test_screen_matches_oracle(ctx, M, lam):
+    rng = np.random.default_rng(M + lam[0])
+    f = rng.integers(-10**6, 10**6, size=M, dtype=np.int64)
+    got = _screen(ctx, f, *lam)
+    want = oracle.screen(f, *lam)
+    assert np.array_equal(got[0], want[0]) and got[1:] == want[1:]
+
+
+@pytest.mark.parametrize("kind", ["constant", "progression", "huge", "negative"])
+def test_screen_special_populations(ctx, kind):
+    M = 5000
+    rng = np.random.default_rng(9)
+    f = {"constant": np.full(M, 42, np.int64),
+         "progression": np.arange(M, dtype=np.int64),
+         "huge": rng.integers(-2 * 10**12, 2 * 10**12, size=M, dtype=np.int64),
+         "negative": -rng.integers(1, 10**9, size=M, dtype=np.int64)}[kind]
+    for lam in [(0, 1), (1, 2), (999, 1000)]:
+        got = _screen(ctx, f, *lam)
+        want = oracle.screen(f, *lam)
+        assert np.array_equal(got[0], want[0]) and got[1:] == want[1:]
+
+
+# --------------------------------------------------------------- ascent ----
+
+ASCENT_CASES = [
+    # n, M, passers (every k-th), density, lo, hi, max_flips
+    (1, 4, 1, 1.0, -100, 100, 0),
+    (5, 50, 1, 1.0, -100, 100, 0),
+    (64, 100, 3, 0.5, -128, 127, 0),
+    (65, 100, 3, 0.5, -128, 127, 0),
+    (129, 64, 2, 0.3, -100, 100, 0),
+    (500, 200, 5, 0.1, -100, 100, 0),
+    (1023, 40, 4, 0.5, -100, 100, 0),
+    (1025, 40, 4, 0.5, -100, 100, 0),
+    (2100, 24, 3, 0.1, -100, 100, 0),
+    (3000, 12, 2, 0.5, -100, 100, 0),
+    (7000, 6, 2, 0.5, -100, 100, 0),
+    (8192, 3, 1, 0.2, -128, 127, 0),
+    (500, 100, 2, 0.3, -100, 100, 7),
+    (130, 60, 2, 0.5, -32768, 32767, 0),
+    (1500, 16, 2, 0.5, -32768, 32767, 0),
+    (2100, 8, 2, 0.3, -1000, 1000, 0),
+    (600, 40, 3, 0.6, -4, 4, 0),          # many ties
+]
+
+
+@pytest.mark.parametrize("n,M,k,d,lo,hi,mf", ASCENT_CASES)
+def test_ascent_matches_oracle(ctx, n, M, k, d, lo, hi, mf):
+    Q = make_instance(n, d, lo, hi, 3000 + n)
+    X = random_candidates(M, n, 4000 + n)
+    f = oracle.eval_many(Q, X, threads=8)
+    idx = np.arange(0, M, k, dtype=np.int32)
+    prob = ctx.problem(Q)
+    Xd, fd = dev(X), dev(f)
+    fl = torch.full((M,), -1, dtype=torch.int32, device="cuda")
+    ctx.ascent(prob, Xd, dev(idx), dev(np.array([len(idx)], np.int64)), fd, fl, max_flips=mf)
+    ctx.sync()
+    Xo, fo, flo = oracle.ascent_many(Q, X, idx, f, max_flips=mf, threads=8)
+    assert np.array_equal(host_u64(Xd), Xo)
+    assert np.array_equal(fd.cpu().numpy(), fo)
+    got_fl = fl.cpu().numpy()
+    assert np.array_equal(got_fl[idx], flo[idx])
+    others = np.setdiff1d(np.arange(M), idx)
+    assert (got_fl[others] == -1).all()
+
+
+def test_ascent_device_count_below_capacity(ctx):
+    """Only the first *n_idx_d listed rows are ascended."""
+    n, M = 300, 40
+    Q = make_instance(n, 0.5, -100, 100, 5)
+    X = random_candidates(M, n, 6)
+    f = oracle.eval_many(Q, X)
+    idx = np.arange(M, dtype=np.int32)
+    prob = ctx.problem(Q)
+    Xd, fd = dev(X), dev(f)
+    fl = torch.zeros(M, dtype=torch.int32, device="cuda")
+    ctx.ascent(prob, Xd, dev(idx), dev(np.array([9], np.int64)), fd, fl)
+    ctx.sync()
+    Xo, fo, _ = oracle.ascent_many(Q, X, idx[:9], f)
+    assert np.array_equal(host_u64(Xd), Xo) and np.array_equal(fd.cpu().numpy(), fo)
+
+
+def test_ascent_rejects_out_of_range_index(ctx):
+    from paper_1706_00037_amd import ubqp
+    n, M = 100, 8
+    Q = make_instance(n, 0.5, -100, 100, 7)
+    X = random_candidates(M, n, 8)
+    prob = ctx.problem(Q)
+    Xd, fd = dev(X), dev(oracle.eval_many(Q, X))
+    fl = torch.zeros(M, dtype=torch.int32, device="cuda")
+    idx = dev(np.array([1, M + 5, 3], np.int32))
+    ctx.ascent(prob, Xd, idx, dev(np.array([3], np.int64)), fd, fl)
+    with pytest.raises(ubqp.UbqpError):
+        ctx.sync()
+    ctx.sync()                                            # the flag was cleared
+
+
+# ------------------------------------------------------------ multistart ----
+
+def _compare_multistart(ctx, Q, **kw):
+    prob = ctx.problem(Q)
+    r = ctx.multistart(prob, **kw)
+    o = oracle.multistart(Q, threads=8, **kw)
+    assert r["have_best"] == o["have_best"]
+    assert np.array_equal(r["stats"], o["stats"]), (r["stats"], o["stats"])
+    assert r["best_f"] == o["best_f"]
+    if o["have_best"]:
+        assert np.array_equal(r["best_x"], o["best_x"])
+    return r, o
+
+
+def test_multistart_config1_full(ctx):
+    """500 variables, 10% density, 1000 candidates per generation, 20 generations."""
+    c = CONFIGS["cfg1"]
+    Q = make_instance(c["n"], c["density"], c["lo"], c["hi"], c["inst_seed"])
+    _compare_multistart(ctx, Q, M=c["M"], H=c["H"], lam_num=c["lam"][0], lam_den=c["lam"][1], G=c["G"],
+                        run_seed=c["run_seed"])
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=200, d=0.5, lo=-32768, hi=32767, M=300, H=10, lam=(1, 2), G=4, mf=0, flags=0),
+    dict(n=333, d=0.2, lo=-100, hi=100, M=999, H=7, lam=(3, 10), G=3, mf=0, flags=1),
+    dict(n=64, d=0.9, lo=-128, hi=127, M=129, H=1, lam=(4, 5), G=6, mf=0, flags=0),
+    dict(n=150, d=0.5, lo=-100, hi=100, M=200, H=10, lam=(1, 2), G=3, mf=3, flags=0),
+    dict(n=90, d=0.5, lo=-100, hi=100, M=100, H=5, lam=(1, 1), G=2, mf=0, flags=0),   # nobody passes
+    dict(n=1100, d=0.3, lo=-100, hi=100, M=2000, H=10, lam=(1, 2), G=3, mf=0, flags=0),
+])
+def test_multistart_matches_oracle(ctx, case):
+    c = case
+    Q = make_instance(c["n"], c["d"], c["lo"], c["hi"], 6000 + c["n"])
+    r, o = _compare_multistart(ctx, Q, M=c["M"], H=c["H"], lam_num=c["lam"][0], lam_den=c["lam"][1], G=c["G"],
+                               max_flips=c["mf"], run_seed=11, flags=c["flags"])
+    if c["lam"] == (1, 1):
+        assert not r["have_best"]
+
+
+def test_multistart_f_dump_matches_oracle(ctx):
+    n, M, G = 120, 240, 3
+    Q = make_instance(n, 0.4, -100, 100, 17)
+    prob = ctx.problem(Q)
+    dump = torch.zeros(G * M, dtype=torch.int64, device="cuda")
+    ctx.multistart(prob, M=M, H=4, lam_num=1, lam_den=3, G=G, run_seed=2, f_dump=dump)
+    o = oracle.multistart(Q, M=M, H=4, lam_num=1, lam_den=3, G=G, run_seed=2, dump=True)
+    assert np.array_equal(dump.cpu().numpy().reshape(G, M), o["f_all"])
+
+
+def test_multistart_deterministic(ctx):
+    Q = make_instance(700, 0.3, -100, 100, 21)
+    prob = ctx.problem(Q)
+    a = ctx.multistart(prob, M=3000, H=10, lam_num=1, lam_den=2, G=3, run_seed=4)
+    b = ctx.multistart(prob, M=3000, H=10, lam_num=1, lam_den=2, G=3, run_seed=4)
+    assert a["best_f"] == b["best_f"] and np.array_equal(a["stats"], b["stats"])
+    assert np.array_equal(a["best_x"], b["best_x"])
+
+
+def test_multistart_result_is_a_local_optimum(ctx):
+    """Larger run: the incumbent's value is its objective and no single flip improves it."""
+    n = 2500
+    Q = make_instance(n, 0.1, -100, 100, 2001)
+    prob = ctx.problem(Q)
+    r = ctx.multistart(prob, M=8192, H=10, lam_num=1, lam_den=2, G=3, run_seed=2)
+    assert r["have_best"]
+    assert oracle.f(Q, r["best_x"]) == r["best_f"]
+    assert (oracle.delta(Q, r["best_x"]) <= 0).all()
+    assert r["stats"][-1, 4] == r["best_f"]
+
+
+def test_run_in_steps_equals_one_call(ctx):
+    """Resuming a run generation by generation gives the uninterrupted result; the
+    timing flag changes nothing but the recorded times."""
+    from paper_1706_00037_amd import ubqp
+    Q = make_instance(400, 0.3, -100, 100, 23)
+    prob = ctx.problem(Q)
+    kw = dict(M=1500, H=10, lam_num=1, lam_den=2, G=5, run_seed=8)
+    one = ctx.multistart(prob, **kw)
+    run = ctx.run(prob, flags=ubqp.UBQP_TIMING, **kw)
+    run.step(2)
+    mid = run.result()
+    assert mid["generations"] == 2 and np.array_equal(mid["stats"], one["stats"][:2])
+    run.step(3)
+    r = run.result()
+    run.close()
+    assert r["generations"] == 5 and r["best_f"] == one["best_f"]
+    assert np.array_equal(r["stats"], one["stats"]) and np.array_equal(r["best_x"], one["best_x"])
+    assert (np.diff(r["gen_ms"]) > 0).all() and (r["phase_ms"] >= 0).all()
+    with pytest.raises(ubqp.UbqpError):
+        ctx.run(prob, **kw).step(6)
