@@ -1,7 +1,7 @@
 // Batched exact objective on int8 matrix cores (the evaluation the paper moves
 // to the GPU, Introduction and Pseudocode section):
 //
-//     Y = X Q  (int8 x int8 -> int32, v_mfma_i32_16x16x64_i8),
+//     Y = X Q  (int8 x int8 -> int32, v_mfma_i32_32x32x32_i8),
 //     f_m = sum_j x_mj Y_mj  (int64)
 //
 // X is bit-packed (1 bit per variable, the A operand is expanded to int8 0/1 in
@@ -13,19 +13,26 @@
 // is summed per 64-column slab in int32 (<= 2^26) and accumulated across slabs
 // and planes with int64 atomics (integer, so the order does not matter).
 //
-// Workgroup tile BM x BN = 256 x 128 (4 waves of 128 x 64), K staged through
-// LDS KC = 128 at a time, double buffered.  A second epilogue stores Y rows
-// instead (the Delta initialisation of the ascent, on gathered passer rows).
+// Workgroup tile BM x BN = 256 x 128: four waves of 64 rows x 128 columns
+// (2 x 4 blocks of 32 x 32), so each expanded A fragment feeds 4 MFMAs.  K is
+// staged through LDS KC = 128 at a time, double buffered (the tail of the last
+// step reads zeros); 48 KB of LDS and under 256 registers per wave let two
+// workgroups share a CU, which hides the global-load latency of the staging.
+// Inside a K step the fragments of substep s+1 are read (and the A bits
+// expanded) while the MFMAs of substep s run, interleaved by scheduling groups.
+// Other epilogues store Y rows or the ascent's keys (the Delta initialisation,
+// on gathered passer rows).
 #include "ubqp_internal.h"
 
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 256, BN = 128, KC = 128, THR = 256;
-constexpr int BPITCH = KC + 16;  // bytes per staged Q row (pad against bank conflicts)
-constexpr int WM = 128, WN = 64;  // wave tile
-constexpr int FM = WM / 16, FN = WN / 16;
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 256, BN = 128, THR = 256;
+constexpr int WM = 64;            // wave tile: the four waves split the 256 rows, each covers all 128 columns
+constexpr int FM = WM / 32, FN = BN / 32;
 
 // 16 bits -> 16 bytes of 0/1: nibble v spreads to bytes by v * 0x00204081
 // (bit i lands at 8i, no carries because the copies are 7 bits apart).
@@ -37,6 +44,16 @@ __device__ inline v4i expand16(uint32_t bits)
     r[2] = (int)((((bits >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
     r[3] = (int)((((bits >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
     return r;
+}
+
+// Sum over the 16 lanes of each DPP row (every lane gets its row's sum).
+__device__ inline int32_t row16_sum(int32_t v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);  // row_ror:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    return v;
 }
 
 struct EvalArgs {
@@ -61,15 +78,24 @@ struct EvalArgs {
 // Epilogues of the contraction.
 enum { EPI_ROWDOT = 0, EPI_Y = 1, EPI_KEYS = 2 };
 
-template <int EPI>
-__global__ __launch_bounds__(THR, 1) void eval_kernel(EvalArgs a)
+// Scheduling groups (the instruction classes of __builtin_amdgcn_sched_group_barrier).
+#define SG_VALU 0x002
+#define SG_MFMA 0x008
+#define SG_DSR 0x100
+
+template <int EPI, int KC>
+__global__ __launch_bounds__(THR, KC == 128 ? 2 : 1) void eval_kernel(EvalArgs a)
 {
     constexpr bool STORE_Y = EPI != EPI_ROWDOT;
+    constexpr int BPITCH = KC + 16;       // bytes per staged Q row (16-byte skew: conflict-free reads)
+    constexpr int APITCH = KC / 64 + 1;   // words per staged X row (odd: conflict-free 8-byte reads)
+    constexpr int NSUB = KC / 32;         // 32-deep MFMA substeps per K step
+    constexpr int BCH = BN * KC / 16 / THR;  // 16-byte Q chunks each thread stages per K step
+    constexpr int BROWS = THR / (KC / 16);   // Q rows covered by one pass of the threads
     __shared__ __align__(16) int8_t Bs[2][BN * BPITCH];
-    __shared__ __align__(16) uint64_t As[2][BM * 2];
+    __shared__ __align__(16) uint64_t As[2][BM * APITCH];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
 
     // XCD-aware tile order: consecutive workgroups go round-robin to the 8 XCDs;
     // give each XCD a contiguous run of tiles, ordered n-tile-major so the
@@ -90,99 +116,140 @@ __global__ __launch_bounds__(THR, 1) void eval_kernel(EvalArgs a)
     const int n0 = nt * BN;
     const int8_t *qp = a.q + plane * a.plane_stride;
 
-    // staging assignment: thread tid loads A row m0 + tid (2 words) and four
-    // 16-byte chunks of the Q block
+    // staging assignment: thread tid loads X row m0 + tid (KC/64 words) and BCH
+    // 16-byte chunks of the Q block (rows tid / (KC/16) + BROWS i, chunk tid % (KC/16))
     const int64_t arow = m0 + tid;
     const uint64_t *xrow = nullptr;
     if (arow < Mrows) {
         const int64_t r = STORE_Y ? (int64_t)a.rows[arow] : arow;
         if (r >= 0 && r < a.x_rows) xrow = a.X + r * a.W;
     }
+    const int brow = tid / (KC / 16), bc16 = tid % (KC / 16);
+    const int8_t *qsrc = qp + (int64_t)(n0 + brow) * a.n_pad + bc16 * 16;
 
-    uint64_t aw0 = 0, aw1 = 0;
-    uint4 br0, br1, br2, br3;
-    // global -> registers for stage kc (A: 2 words of row m0 + tid; B: four 16-byte chunks)
-#define EVAL_LOAD_STAGE(kc)                                                                    \
-    do {                                                                                       \
-        const int w_ = (kc) * (KC / 64);                                                       \
-        aw0 = (xrow && w_ < a.W) ? xrow[w_] : 0ull;                                            \
-        aw1 = (xrow && w_ + 1 < a.W) ? xrow[w_ + 1] : 0ull;                                    \
-        const int8_t *qb_ = qp + (int64_t)(n0 + (tid >> 3)) * a.n_pad + (kc) * KC + (tid & 7) * 16; \
-        const int64_t rs_ = (int64_t)(THR / 8) * a.n_pad;                                      \
-        br0 = *(const uint4 *)(qb_);                                                           \
-        br1 = *(const uint4 *)(qb_ + rs_);                                                     \
-        br2 = *(const uint4 *)(qb_ + 2 * rs_);                                                 \
-        br3 = *(const uint4 *)(qb_ + 3 * rs_);                                                 \
+    uint64_t aw[KC / 64];
+    uint4 br[BCH];
+    const int nk = (a.n_pad + KC - 1) / KC;
+    // global -> registers for K step kc; columns past n_pad (the tail of the last step) read as 0
+#define EVAL_LOAD_STAGE(kc)                                                                   \
+    do {                                                                                      \
+        _Pragma("unroll") for (int w_ = 0; w_ < KC / 64; w_++) {                              \
+            const int wi_ = (kc) * (KC / 64) + w_;                                            \
+            aw[w_] = (xrow && wi_ < a.W) ? xrow[wi_] : 0ull;                                  \
+        }                                                                                     \
+        const bool kin_ = (kc) * KC + bc16 * 16 < a.n_pad;                                    \
+        _Pragma("unroll") for (int i_ = 0; i_ < BCH; i_++) {                                  \
+            br[i_] = kin_ ? *(const uint4 *)(qsrc + (int64_t)(BROWS * i_) * a.n_pad + (kc) * KC) \
+                          : uint4{0u, 0u, 0u, 0u};                                            \
+        }                                                                                     \
     } while (0)
     // registers -> LDS buffer buf
-#define EVAL_STORE_STAGE(buf)                                                                  \
-    do {                                                                                       \
-        As[buf][tid * 2] = aw0;                                                                \
-        As[buf][tid * 2 + 1] = aw1;                                                            \
-        int8_t *bs_ = &Bs[buf][(tid >> 3) * BPITCH + (tid & 7) * 16];                          \
-        *(uint4 *)(bs_) = br0;                                                                 \
-        *(uint4 *)(bs_ + (THR / 8) * BPITCH) = br1;                                            \
-        *(uint4 *)(bs_ + 2 * (THR / 8) * BPITCH) = br2;                                        \
-        *(uint4 *)(bs_ + 3 * (THR / 8) * BPITCH) = br3;                                        \
+#define EVAL_STORE_STAGE(buf)                                                                 \
+    do {                                                                                      \
+        _Pragma("unroll") for (int w_ = 0; w_ < KC / 64; w_++) As[buf][tid * APITCH + w_] = aw[w_]; \
+        _Pragma("unroll") for (int i_ = 0; i_ < BCH; i_++)                                    \
+            *(uint4 *)(&Bs[buf][(brow + BROWS * i_) * BPITCH + bc16 * 16]) = br[i_];          \
     } while (0)
 
-    v4i acc[FM][FN];
+    v16i acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; i++)
 #pragma unroll
-        for (int k = 0; k < FN; k++) acc[i][k] = v4i{0, 0, 0, 0};
+        for (int k = 0; k < FN; k++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) acc[i][k][e] = 0;
 
-    const int nk = a.n_pad / KC;
+    // Fragments of a 32-deep substep: lane l holds row / column l%32 and the 16
+    // consecutive k starting at 16 (l/32) -- the same k for A and B.
+    const int r32 = lane & 31, h = lane >> 5;
+    v4i afc[FM], afn[FM], bfc[FN], bfn[FN];
+    uint64_t awd[FM];
+#define EVAL_READ_A(buf, w)                                                                   \
+    _Pragma("unroll") for (int mi = 0; mi < FM; mi++)                                         \
+        awd[mi] = As[buf][(wave * WM + mi * 32 + r32) * APITCH + (w)]
+#define EVAL_EXPAND_A(dst, half)                                                              \
+    _Pragma("unroll") for (int mi = 0; mi < FM; mi++)                                         \
+        dst[mi] = expand16((uint32_t)(awd[mi] >> (32 * (half) + 16 * h)) & 0xFFFFu)
+#define EVAL_READ_B(dst, buf, sub)                                                            \
+    _Pragma("unroll") for (int ni = 0; ni < FN; ni++)                                         \
+        dst[ni] = *(const v4i *)(&Bs[buf][(ni * 32 + r32) * BPITCH + 32 * (sub) + 16 * h])
+
     EVAL_LOAD_STAGE(0);
     EVAL_STORE_STAGE(0);
     __syncthreads();
-    const int g = lane >> 4, r16 = lane & 15;
+    EVAL_READ_A(0, 0);
+    EVAL_READ_B(bfc, 0, 0);
+    EVAL_EXPAND_A(afc, 0);
     for (int kc = 0; kc < nk; kc++) {
         const int cur = kc & 1;
-        if (kc + 1 < nk) EVAL_LOAD_STAGE(kc + 1);
+        const bool more = kc + 1 < nk;
+        if (more) EVAL_LOAD_STAGE(kc + 1);
 #pragma unroll
-        for (int ks = 0; ks < KC / 64; ks++) {
-            v4i bf[FN];
-#pragma unroll
-            for (int ni = 0; ni < FN; ni++) {
-                const int nrow = wn * WN + ni * 16 + r16;
-                bf[ni] = *(const v4i *)(&Bs[cur][nrow * BPITCH + ks * 64 + g * 16]);
+        for (int sub = 0; sub < NSUB; sub++) {
+            if (sub + 1 < NSUB) {
+                // next substep's fragments: reads first, MFMAs, then the A expansion
+                if (((sub + 1) & 1) == 0) EVAL_READ_A(cur, (sub + 1) >> 1);
+                EVAL_READ_B(bfn, cur, sub + 1);
             }
 #pragma unroll
-            for (int mi = 0; mi < FM; mi++) {
-                const int mrow = wm * WM + mi * 16 + r16;
-                const uint64_t word = As[cur][mrow * 2 + ks];
-                const v4i af = expand16((uint32_t)(word >> (g * 16)) & 0xFFFFu);
+            for (int ni = 0; ni < FN; ni++)
 #pragma unroll
-                for (int ni = 0; ni < FN; ni++)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[ni], acc[mi][ni], 0, 0, 0);
+                for (int mi = 0; mi < FM; mi++)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(afc[mi], bfc[ni], acc[mi][ni], 0, 0, 0);
+            if (sub + 1 < NSUB) {
+                EVAL_EXPAND_A(afn, (sub + 1) & 1);
+                // interleave: one MFMA, one LDS read, three VALU
+#pragma unroll
+                for (int i = 0; i < FM * FN; i++) {
+                    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(SG_DSR, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(SG_VALU, 3, 0);
+                }
+#pragma unroll
+                for (int mi = 0; mi < FM; mi++) afc[mi] = afn[mi];
+#pragma unroll
+                for (int ni = 0; ni < FN; ni++) bfc[ni] = bfn[ni];
             }
         }
-        if (kc + 1 < nk) {
+        if (more) {
             EVAL_STORE_STAGE(cur ^ 1);
             __syncthreads();
+            EVAL_READ_A(cur ^ 1, 0);
+            EVAL_READ_B(bfc, cur ^ 1, 0);
+            EVAL_EXPAND_A(afc, 0);
         }
     }
+#undef EVAL_LOAD_STAGE
+#undef EVAL_STORE_STAGE
+#undef EVAL_READ_A
+#undef EVAL_EXPAND_A
+#undef EVAL_READ_B
 
-    // D layout of a 16x16 block: lane holds rows 4*(lane/16) + r, column lane%16.
-    if constexpr (!STORE_Y) {
+    // D layout of a 32x32 block: accumulator e of lane l is row 8 (e/4) + 4 (l/32) + e%4,
+    // column l%32.  The 128 columns of the tile are X words n0/64 and n0/64 + 1.
+    const int word0 = n0 >> 6;
+    if constexpr (EPI == EPI_ROWDOT) {
         const int64_t wgt = plane == 0 ? a.weight0 : 1;
-        const int word = (n0 + wn * WN) >> 6;  // the wave's 64 columns are one X word
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int64_t row = m0 + wm * WM + mi * 16 + g * 4 + r;
-                uint64_t xw = 0;
-                if (row < Mrows && word < a.W) xw = a.X[row * a.W + word];
+            for (int e = 0; e < 16; e++) {
+                const int64_t row = m0 + wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                uint64_t xw0 = 0, xw1 = 0;
+                if (row < Mrows) {
+                    if (word0 < a.W) xw0 = a.X[row * a.W + word0];
+                    if (word0 + 1 < a.W) xw1 = a.X[row * a.W + word0 + 1];
+                }
                 int s = 0;
 #pragma unroll
-                for (int ni = 0; ni < FN; ni++) s += ((xw >> (ni * 16 + r16)) & 1ull) ? acc[mi][ni][r] : 0;
-                s += __shfl_xor(s, 1);
-                s += __shfl_xor(s, 2);
-                s += __shfl_xor(s, 4);
-                s += __shfl_xor(s, 8);
-                if (r16 == 0 && row < Mrows && s != 0)
+                for (int ni = 0; ni < FN; ni++) {
+                    const uint64_t xw = ni < 2 ? xw0 : xw1;
+                    s += ((xw >> (32 * (ni & 1) + r32)) & 1ull) ? acc[mi][ni][e] : 0;
+                }
+                // |s| <= 4 * 128 n <= 2^22: the 32-lane sum stays inside int32
+                s = row16_sum(s);
+                s += __shfl_xor(s, 16);
+                if (r32 == 0 && row < Mrows && s != 0)
                     atomicAdd((unsigned long long *)&a.f[row], (unsigned long long)(wgt * (int64_t)s));
             }
         }
@@ -191,35 +258,36 @@ __global__ __launch_bounds__(THR, 1) void eval_kernel(EvalArgs a)
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int64_t row = m0 + wm * WM + mi * 16 + g * 4 + r;
+            for (int e = 0; e < 16; e++) {
+                const int64_t row = m0 + wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
                 if (row < Mrows) {
 #pragma unroll
-                    for (int ni = 0; ni < FN; ni++)
-                        Yp[row * a.n_pad + n0 + wn * WN + ni * 16 + r16] = acc[mi][ni][r];
+                    for (int ni = 0; ni < FN; ni++) Yp[row * a.n_pad + n0 + ni * 32 + r32] = acc[mi][ni][e];
                 }
             }
         }
     } else {
         // Ascent keys of the single-plane problem: with y = (x Q)_j and s = 1 - 2 x_j,
         // Delta_j = q_jj + 2 s y_j, key_j = Delta_j * 256 + 2 (127 - j mod PL) + x_j.
-        const int word = (n0 + wn * WN) >> 6;
         int32_t dg[FN];
 #pragma unroll
-        for (int ni = 0; ni < FN; ni++) dg[ni] = a.diag[n0 + wn * WN + ni * 16 + r16];
+        for (int ni = 0; ni < FN; ni++) dg[ni] = a.diag[n0 + ni * 32 + r32];
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int64_t row = m0 + wm * WM + mi * 16 + g * 4 + r;
+            for (int e = 0; e < 16; e++) {
+                const int64_t row = m0 + wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
                 if (row < Mrows) {
                     const int64_t xr = a.rows[row];
-                    const uint64_t xw = (xr >= 0 && xr < a.x_rows && word < a.W) ? a.X[xr * a.W + word] : 0ull;
+                    const bool ok = xr >= 0 && xr < a.x_rows;
+                    const uint64_t xw0 = (ok && word0 < a.W) ? a.X[xr * a.W + word0] : 0ull;
+                    const uint64_t xw1 = (ok && word0 + 1 < a.W) ? a.X[xr * a.W + word0 + 1] : 0ull;
 #pragma unroll
                     for (int ni = 0; ni < FN; ni++) {
-                        const int col = n0 + wn * WN + ni * 16 + r16;
-                        const int32_t xj = (int32_t)((xw >> (ni * 16 + r16)) & 1ull);
-                        const int32_t y2 = 2 * acc[mi][ni][r];
+                        const int col = n0 + ni * 32 + r32;
+                        const uint64_t xw = ni < 2 ? xw0 : xw1;
+                        const int32_t xj = (int32_t)((xw >> (32 * (ni & 1) + r32)) & 1ull);
+                        const int32_t y2 = 2 * acc[mi][ni][e];
                         const int32_t delta = dg[ni] + (xj ? -y2 : y2);
                         a.Y[row * a.n_pad + col] = delta * 256 + 2 * (127 - col % a.keys_pl) + xj;
                     }
@@ -243,6 +311,10 @@ __global__ __launch_bounds__(256) void eval_init(const uint64_t *__restrict__ X,
     }
     f[c] = v;
 }
+
+#ifndef EVAL_KC
+#define EVAL_KC 128
+#endif
 
 EvalArgs make_args(const ubqp_problem *p, const uint64_t *X, int64_t M)
 {
@@ -268,7 +340,7 @@ hipError_t ubqp_launch_eval(hipStream_t st, const ubqp_problem *p, const uint64_
     EvalArgs a = make_args(p, X, M);
     a.f = f;
     const int64_t T = (int64_t)a.m_tiles * a.n_tiles;
-    hipLaunchKernelGGL(eval_kernel<EPI_ROWDOT>, dim3((unsigned)T, p->planes), dim3(THR), 0, st, a);
+    hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, EVAL_KC>), dim3((unsigned)T, p->planes), dim3(THR), 0, st, a);
     return hipGetLastError();
 }
 
@@ -285,9 +357,9 @@ hipError_t ubqp_launch_yrows(hipStream_t st, const ubqp_problem *p, const uint64
     if (p->planes == 1) {
         a.diag = p->diag;
         a.keys_pl = p->ncol_a / 64;
-        hipLaunchKernelGGL(eval_kernel<EPI_KEYS>, dim3((unsigned)T, 1), dim3(THR), 0, st, a);
+        hipLaunchKernelGGL((eval_kernel<EPI_KEYS, EVAL_KC>), dim3((unsigned)T, 1), dim3(THR), 0, st, a);
     } else {
-        hipLaunchKernelGGL(eval_kernel<EPI_Y>, dim3((unsigned)T, p->planes), dim3(THR), 0, st, a);
+        hipLaunchKernelGGL((eval_kernel<EPI_Y, EVAL_KC>), dim3((unsigned)T, p->planes), dim3(THR), 0, st, a);
     }
     return hipGetLastError();
 }
