@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-e1", action="store_true")
     ap.add_argument("--lam", default="1/2")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device, a dispatch of known traffic for counter calibration")
     return ap.parse_args()
 
 
@@ -100,6 +102,13 @@ def main():
     from paper_1706_00037_amd.inputs import CONFIGS, make_instance, random_candidates
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 1 GiB read, 1 GiB written")
+        del src, dst
     c = CONFIGS["cfg3"]
     n, M, H = c["n"], c["M"], c["H"]
     lam_num, lam_den = (int(t) for t in args.lam.split("/"))
