@@ -14,7 +14,9 @@ value = candidates evaluated and processed per second over the timed
 generations (whole path).  Also reported: the batched evaluation alone, the
 paper's Table 1 replica (1000 random solutions, n = 2500..7000), the roofline
 of the dominant kernel from stream events recorded around each phase during the
-timed generations, and the CPU oracle timed on a bounded sample.
+timed generations, the CPU oracle timed on a bounded sample, and the serving
+form: solves/s and p50/p99 latency of Poisson-arriving solve requests against
+the request server, beside the same server admitting one request at a time.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -50,6 +52,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-e1", action="store_true")
     ap.add_argument("--lam", default="1/2")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-active", type=int, default=32)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 1 GiB device-to-device, a dispatch of known traffic for counter calibration")
     return ap.parse_args()
@@ -88,6 +95,158 @@ def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
                        f"P={P_per_gen:.0f}, F={flips_per_gen:.0f}",
                 ms_per_step=t_gen * 1e3, eval_only_evals_per_s=threads / t_eval,
                 t_eval_ms=t_eval * 1e3, t_init_ms=t_init * 1e3, t_flip_us=t_flip * 1e6)
+
+
+def make_request_instance(torch, n, density, seed):
+    """Symmetric int8 instance for the serving trace, drawn on the device with
+    torch's seeded Philox generator and copied to page-locked host memory:
+    upper-triangle mask Bernoulli(density) (diagonal included), values uniform in
+    [-100, 100] \\ {0}, mirrored."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    u = torch.randint(0, 200, (n, n), generator=g, device="cuda", dtype=torch.int16)
+    v = torch.where(u >= 100, u - 99, u - 100)
+    keep = torch.rand((n, n), generator=g, device="cuda") < density
+    U = torch.triu(torch.where(keep, v, torch.zeros_like(v)))
+    Q = (U + torch.tril(U.t(), -1)).to(torch.int8)
+    host = torch.empty((n, n), dtype=torch.int8, pin_memory=True)
+    host.copy_(Q)
+    return host
+
+
+def serving_bench(ctx, ubqp, torch, R=300, warm=20, rate=200.0, distinct=32, max_active=32,
+                  pool_gib=48, seed=5):
+    """Poisson arrivals of multi-start solve requests (n ~ U{500..7000}, density ~
+    U[0.05, 1], [-100, 100], M=4096, H=10, lambda=1/2, G=10) against the request
+    server, then against the same server admitting one request at a time (the
+    plain one-at-a-time GPU loop).  Latency = result on the host - scheduled
+    arrival (upload included)."""
+    import threading
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.integers(500, 7001, size=distinct)
+    ds = rng.uniform(0.05, 1.0, size=distinct)
+    log(f"[serve] generating {distinct} distinct instances into page-locked memory")
+    inst = []
+    for k in range(distinct):
+        inst.append(make_request_instance(torch, int(ns[k]), float(ds[k]), 5000 + k))
+    gaps = rng.exponential(1.0 / rate, size=R)
+    offs = np.cumsum(gaps) - gaps[0]
+    pr = lambda r: dict(M=4096, H=10, lam_num=1, lam_den=2, G=10, run_seed=5000 + r)
+
+    def run_trace(active):
+        srv = ctx.server(pool_bytes=pool_gib << 30, max_active=active)
+        try:
+            ids = [srv.submit(inst[r % distinct], **pr(10**6 + r)) for r in range(warm)]
+            got = 0
+            while got < len(ids):
+                got += len(srv.wait(timeout_s=5.0))
+            done = {}
+            stop = threading.Event()
+
+            def collect():
+                while len(done) < R and not stop.is_set():
+                    for x in srv.wait(timeout_s=0.5):
+                        done[x["id"]] = x
+            th = threading.Thread(target=collect)
+            th.start()
+            t0 = time.monotonic_ns() + 20_000_000
+            sched = {}
+            for r in range(R):
+                at = t0 + int(offs[r] * 1e9)
+                while True:
+                    dt = at - time.monotonic_ns()
+                    if dt <= 0:
+                        break
+                    time.sleep(min(dt, 2_000_000) / 1e9)
+                i = srv.submit(inst[r % distinct], **pr(r))
+                sched[i] = at
+            th.join(timeout=600)
+            stop.set()
+            st = srv.stats()
+        finally:
+            srv.close()
+        assert len(done) == R, f"{len(done)} of {R} requests finished"
+        assert all(x["status"] == ubqp.UBQP_OK for x in done.values())
+        lat = np.array([(done[i]["t_done_ns"] - sched[i]) / 1e6 for i in sched])
+        end = max(x["t_done_ns"] for x in done.values())
+        span = (end - t0) / 1e9
+        return dict(solves_per_s=R / span, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()), span_s=span,
+                    max_running=st["max_running"], generations=st["generations"],
+                    pool_high_gib=st["pool_high"] / 2**30, max_active=active)
+
+    log(f"[serve] trace: {R} requests at {rate}/s, continuous batching (max_active={max_active})")
+    batched = run_trace(max_active)
+    log(f"[serve] batched: {batched}")
+    log("[serve] same trace, one request at a time")
+    plain = run_trace(1)
+    log(f"[serve] one at a time: {plain}")
+    return dict(batched=batched, one_at_a_time=plain, requests=R, warmup_requests=warm, rate_per_s=rate,
+                distinct_instances=distinct,
+                workload=f"Poisson {rate:.0f} req/s; n ~ U{{500..7000}}, density ~ U[0.05,1], [-100,100], "
+                         f"M=4096, H=10, lambda=1/2, G=10; {distinct} distinct seeded instances cycled, "
+                         f"a fresh run seed and a fresh upload per request")
+
+
+def make_wide_instance(torch, n, density, seed):
+    """Symmetric int16 instance for the batched workload, drawn on the device with
+    torch's seeded Philox generator: upper-triangle mask Bernoulli(density)
+    (diagonal included), values uniform in [-32768, 32767] \\\\ {0}, mirrored."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    u = torch.randint(-32768, 32767, (n, n), generator=g, device="cuda", dtype=torch.int32)
+    v = torch.where(u >= 0, u + 1, u)
+    keep = torch.rand((n, n), generator=g, device="cuda") < density
+    U = torch.triu(torch.where(keep, v, torch.zeros_like(v)))
+    return (U + torch.tril(U.t(), -1)).to(torch.int16).cpu().numpy()
+
+
+def batched_bench(ctx, ubqp, torch, count=64, G=6, warm=2, seed=4):
+    """64 instances, n ~ U{1000..7000}, density in {0.1, 0.5, 1.0}, int16
+    coefficients (two int8 planes each), M = 4096, lambda = 1/2: one batch whose
+    generation is one launch per step covering every instance (captured as a HIP
+    graph), against the same instances run one after another."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.integers(1000, 7001, size=count)
+    ds = rng.choice([0.1, 0.5, 1.0], size=count)
+    log(f"[batch] uploading {count} int16 instances")
+    probs = [ctx.problem(make_wide_instance(torch, int(ns[k]), float(ds[k]), 4001 + k)) for k in range(count)]
+    assert all(p.planes == 2 for p in probs)
+    params = [dict(M=4096, H=10, lam_num=1, lam_den=2, G=G, run_seed=4000 + k) for k in range(count)]
+    ops = sum(2.0 * 4096 * int(n) * int(n) * 2 for n in ns)         # dense xQx work of one generation, 2 planes
+    b = ctx.batch(probs, params)
+    b.step(warm)
+    b.result(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(G - warm)
+    res = [b.result(k) for k in range(count)]
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / (G - warm)
+    b.close()
+    log(f"[batch] batched: {t_batch * 1e3:.2f} ms per generation of all {count} instances")
+    # the same generations, one instance after another
+    t_seq = 0.0
+    for k in range(count):
+        r = ctx.run(probs[k], **params[k])
+        r.step(warm)
+        r.result()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.step(G - warm)
+        rr = r.result()
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        r.close()
+        assert rr["best_f"] == res[k]["best_f"] and np.array_equal(rr["stats"], res[k]["stats"]), k
+    t_seq /= (G - warm)
+    log(f"[batch] one instance at a time: {t_seq * 1e3:.2f} ms per generation of all {count}")
+    return dict(instances=count, ms_per_generation=t_batch * 1e3, evals_per_s=count * 4096 / t_batch,
+                dense_tops=ops / t_batch / 1e12, sequential_ms_per_generation=t_seq * 1e3,
+                speedup_vs_sequential=t_seq / t_batch, timed_generations=G - warm,
+                workload="64 instances, n ~ U{1000..7000}, density in {0.1,0.5,1.0}, int16 coefficients "
+                         "(hi/lo int8 planes), M=4096, H=10, lambda=1/2")
 
 
 def main():
@@ -198,6 +357,17 @@ def main():
                                    speedup_vs_paper_gpu=PAPER_TABLE1_S[nn] * 1e3 / ms)
             log(f"[bench] 1000 evals n={nn}: {ms:.3f} ms (paper GTX 780 Ti: {PAPER_TABLE1_S[nn]} s)")
 
+    # ---- batched form: 64 int16 instances per launch ----------------------------------
+    batched = None
+    if not args.no_batch:
+        batched = batched_bench(ctx, ubqp, torch)
+
+    # ---- serving: Poisson arrivals against the request server -------------------------
+    serving = None
+    if not args.no_serve:
+        serving = serving_bench(ctx, ubqp, torch, R=args.serve_requests, rate=args.serve_rate,
+                                max_active=args.serve_active)
+
     # ---- CPU oracle -----------------------------------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -232,6 +402,8 @@ def main():
                       "useful_tops": useful_ops / eval_ms / 1e9, "executed_tops": exec_ops / eval_ms / 1e9,
                       "frac_int8_peak": useful_ops / eval_ms / 1e9 / INT8_PEAK_TOPS},
         "e1_replica": e1_rep,
+        "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -52,6 +52,7 @@ extern "C" {
 /* flags of ubqp_params */
 #define UBQP_DERIV_START 1u /* generation-0 seed 0 is the first-derivative solution */
 #define UBQP_TIMING 2u      /* record stream events around every phase of a generation */
+#define UBQP_NO_GRAPH 4u    /* launch every kernel directly instead of replaying a captured generation */
 
 /* phases of a generation, in order (ubqp_result.phase_ms_host) */
 #define UBQP_PHASE_DIVERSIFY 0
@@ -74,7 +75,7 @@ typedef struct {
     int32_t lam_den;
     int32_t G;          /* generations (iterations of the main loop), >= 1             */
     int32_t max_flips;  /* flips per ascent, 0 = until a 1-flip local optimum          */
-    uint32_t flags;     /* UBQP_DERIV_START | UBQP_TIMING                              */
+    uint32_t flags;     /* UBQP_DERIV_START | UBQP_TIMING | UBQP_NO_GRAPH              */
     uint64_t run_seed;  /* SplitMix64 seed of the random solutions                     */
 } ubqp_params;
 
@@ -92,7 +93,8 @@ typedef struct {
                             /*   created with UBQP_TIMING; left untouched otherwise)       */
 } ubqp_result;
 
-typedef struct ubqp_run ubqp_run;  /* library-owned: the device state of one multi-start run */
+typedef struct ubqp_run ubqp_run;      /* library-owned: the device state of one multi-start run */
+typedef struct ubqp_batch ubqp_batch;  /* library-owned: several runs advanced together          */
 
 /* Create a context on HIP device `device` that launches on `stream` (a
  * hipStream_t; 0 is the null stream).  *out receives the handle. */
@@ -116,6 +118,11 @@ UBQP_API int ubqp_sync(ubqp_ctx *ctx);
  * UBQP_ENOMEM.
  */
 UBQP_API int ubqp_problem_create(ubqp_ctx *ctx, int32_t n, const int32_t *q_host, ubqp_problem **out);
+/* The same from coefficients of elem_bytes = 1 (int8), 2 (int16) or 4 (int32)
+ * bytes each.  The checks and the conversion to the resident layout run on the
+ * device; the host only copies the n x n coefficients. */
+UBQP_API int ubqp_problem_create_typed(ubqp_ctx *ctx, int32_t n, const void *q_host, int32_t elem_bytes,
+                                       ubqp_problem **out);
 UBQP_API int ubqp_problem_destroy(ubqp_problem *prob);
 /* n, padded size n_pad (a multiple of 128) and number of int8 planes (1 or 2). */
 UBQP_API int ubqp_problem_info(const ubqp_problem *prob, int32_t *n, int32_t *n_pad, int32_t *planes);
@@ -196,6 +203,88 @@ UBQP_API int ubqp_run_destroy(ubqp_run *run);
 /* The whole loop in one synchronous call: create, params->G steps, result, destroy. */
 UBQP_API int ubqp_multistart(ubqp_ctx *ctx, const ubqp_problem *prob, const ubqp_params *params,
                              int64_t *f_dump_d, ubqp_result *result);
+
+/*
+ * Batched form: `count` independent multi-start runs (instance i: probs[i],
+ * params[i]; sizes, coefficient widths and parameters may all differ, the
+ * generation count G must be equal) advanced together.  Each step of a
+ * generation is one launch covering every instance: the grid is the
+ * concatenation of the instances' work (candidate tiles, passer waves, seed
+ * words), and a block finds its instance from a prefix table.  Unless
+ * UBQP_NO_GRAPH or UBQP_TIMING is set in params[0].flags, the launches of a
+ * generation are captured once as a HIP graph and replayed.  Every instance's
+ * result equals the result of running it alone.
+ * ubqp_batch_result(batch, i, result) waits and fills instance i's result.
+ */
+UBQP_API int64_t ubqp_batch_footprint(int32_t count, const ubqp_problem *const *probs, const ubqp_params *params);
+UBQP_API int ubqp_batch_create(ubqp_ctx *ctx, int32_t count, const ubqp_problem *const *probs,
+                               const ubqp_params *params, ubqp_batch **out);
+UBQP_API int ubqp_batch_step(ubqp_batch *batch, int32_t generations);
+UBQP_API int ubqp_batch_result(ubqp_batch *batch, int32_t i, ubqp_result *result);
+UBQP_API int ubqp_batch_destroy(ubqp_batch *batch);
+/* create, G steps, every result, destroy */
+UBQP_API int ubqp_multistart_batched(ubqp_ctx *ctx, int32_t count, const ubqp_problem *const *probs,
+                                     const ubqp_params *params, ubqp_result *results);
+
+/*
+ * Serving form: a request loop that runs multi-start solves as they arrive,
+ * several at a time, on one device.  A request is a problem given as host
+ * coefficients plus its parameters; its result equals the result of running it
+ * alone (ubqp_problem_create_typed + ubqp_multistart).
+ *
+ * The server owns a device memory pool of pool_bytes and a worker thread.
+ * Requests wait in FIFO order; the worker admits the oldest one when fewer than
+ * max_active requests are admitted and the pool has room for its footprint
+ * (ubqp_request_footprint: resident Q planes and ascent matrix, population,
+ * objectives, Delta workspace, seeds).  An admitted request's coefficients are
+ * copied and converted on a second stream while admitted requests compute.  At
+ * every generation boundary the requests whose upload has finished join, and
+ * one batched generation (the launches of the batched form) advances every
+ * running request; a request leaves after its G generations and its memory
+ * returns to the pool.  No request's work waits for another's to finish.
+ *
+ * Coefficients: elem_bytes = 1 (int8, one plane) or 2 (int16, hi/lo planes) or
+ * 4 (int32 within [-32768, 32767], hi/lo planes).  q_host, best_x_host (W words)
+ * and stats_host (G x 5, may be NULL) must stay valid until the request is
+ * reported done; page-locked q_host makes the upload asynchronous.  params.flags
+ * may hold UBQP_DERIV_START only.
+ *
+ * ubqp_server_wait blocks until at least one request has finished or timeout_us
+ * (< 0: no limit) has passed, and moves up to `max` finished requests into
+ * done[] (*count of them).  ubqp_server_destroy finishes every submitted request,
+ * then releases the server.  Calls may come from any thread; the ubqp_ctx given
+ * at creation belongs to the server until it is destroyed.
+ */
+typedef struct ubqp_server ubqp_server;
+typedef struct {
+    int64_t id;             /* as returned by ubqp_server_submit                          */
+    int32_t status;         /* UBQP_OK, or the error that ended the request               */
+    int32_t generations;    /* generations completed                                      */
+    int64_t best_f;         /* incumbent value (INT64_MIN if none)                        */
+    int32_t have_best;
+    int32_t planes;         /* int8 planes the request's Q used (1 or 2)                  */
+    int64_t t_submit_ns;    /* CLOCK_MONOTONIC times: submitted, admitted, first          */
+    int64_t t_admit_ns;     /*   generation queued, results on the host                   */
+    int64_t t_start_ns;
+    int64_t t_done_ns;
+} ubqp_request_info;
+
+/* Pool bytes a request occupies while admitted (-1 if the arguments are invalid). */
+UBQP_API int64_t ubqp_request_footprint(int32_t n, int32_t elem_bytes, const ubqp_params *params);
+UBQP_API int ubqp_server_create(ubqp_ctx *ctx, int64_t pool_bytes, int32_t max_active, ubqp_server **out);
+/* Errors: UBQP_EINVAL (arguments, or a footprint larger than the whole pool). */
+UBQP_API int ubqp_server_submit(ubqp_server *server, int32_t n, const void *q_host, int32_t elem_bytes,
+                                const ubqp_params *params, uint64_t *best_x_host, int64_t *stats_host,
+                                int64_t *id);
+UBQP_API int ubqp_server_wait(ubqp_server *server, int64_t timeout_us, ubqp_request_info *done, int32_t max,
+                              int32_t *count);
+/* Counters: {submitted, finished, failed, generations launched, most requests
+ * running in one generation, pool high-water bytes, requests waiting, requests
+ * admitted}. */
+UBQP_API int ubqp_server_stats(ubqp_server *server, int64_t out[8]);
+/* Message of the last server-level failure (never NULL). */
+UBQP_API const char *ubqp_server_error(ubqp_server *server);
+UBQP_API int ubqp_server_destroy(ubqp_server *server);
 
 #ifdef __cplusplus
 }

@@ -31,24 +31,6 @@
 
 namespace {
 
-struct AscArgs {
-    const void *qa;         // zero diagonal: int8 [n_pad][ncol_a] or int16 [n_pad][n_pad]
-    int32_t ncol_a;         // columns of the int8 ascent matrix (1024 NB)
-    const int32_t *diag;
-    int32_t n, n_pad, W, planes;
-    int64_t weight0, bias;
-    uint64_t *X;
-    int64_t x_rows;
-    const int32_t *idx;
-    const int64_t *nidx_d;  // length of the whole list
-    int64_t offset;         // first list entry of this chunk
-    int64_t max_idx;        // chunk capacity
-    const int32_t *Y;       // [planes][max_idx][n_pad], row r for list entry offset + r
-    int64_t *f;
-    int32_t *flips;
-    int32_t max_flips, safety_cap;
-    int32_t *err;
-};
 
 template <typename QT> struct RowLoad;
 template <> struct RowLoad<int8_t> {
@@ -384,62 +366,64 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
     }
 }
 
+// One wave per workgroup: a wave whose candidate needs few flips retires at once
+// and its slot is refilled, instead of idling until the slowest wave of a group.
 template <int NB>
-__global__ __launch_bounds__(256) void ascent_i8_kernel(AscArgs a)
+__global__ __launch_bounds__(64) void ascent_i8_kernel(AscArgs a)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x;
     int64_t P = *a.nidx_d - a.offset;
     P = P < a.max_idx ? P : a.max_idx;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < P; p += nw) ascend_i8<NB>(a, p, lane);
+    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_i8<NB>(a, p, lane);
 }
 
 template <int NB, typename QT>
-__global__ __launch_bounds__(256) void ascent_kernel(AscArgs a)
+__global__ __launch_bounds__(64) void ascent_kernel(AscArgs a)
 {
-    const int lane = threadIdx.x & 63;
     int64_t P = *a.nidx_d - a.offset;
     P = P < a.max_idx ? P : a.max_idx;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < P; p += nw) ascend_one<NB, QT>(a, p, lane);
+    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_one<NB, QT>(a, p, threadIdx.x);
 }
 
-template <typename QT>
-hipError_t launch_nb(hipStream_t st, const AscArgs &a, int nb, unsigned blocks)
+template <int NB, typename QT>
+__global__ __launch_bounds__(64) void ascent_batched(const AscArgs *args, const int64_t *prefix, int count)
 {
-    switch (nb) {
-    case 1: hipLaunchKernelGGL((ascent_kernel<1, QT>), dim3(blocks), dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((ascent_kernel<2, QT>), dim3(blocks), dim3(256), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((ascent_kernel<3, QT>), dim3(blocks), dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((ascent_kernel<4, QT>), dim3(blocks), dim3(256), 0, st, a); break;
-    case 5: hipLaunchKernelGGL((ascent_kernel<5, QT>), dim3(blocks), dim3(256), 0, st, a); break;
-    case 6: hipLaunchKernelGGL((ascent_kernel<6, QT>), dim3(blocks), dim3(256), 0, st, a); break;
-    case 7: hipLaunchKernelGGL((ascent_kernel<7, QT>), dim3(blocks), dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((ascent_kernel<8, QT>), dim3(blocks), dim3(256), 0, st, a); break;
-    }
-    return hipGetLastError();
+    const int i = ubqp_find_inst(prefix, count, blockIdx.x);
+    const AscArgs a = args[i];
+    const int64_t w0 = blockIdx.x - prefix[i], nw = prefix[i + 1] - prefix[i];
+    int64_t P = *a.nidx_d - a.offset;
+    P = P < a.max_idx ? P : a.max_idx;
+    for (int64_t p = w0; p < P; p += nw) ascend_one<NB, QT>(a, p, threadIdx.x);
 }
 
-hipError_t launch_i8(hipStream_t st, const AscArgs &a, int nb, unsigned blocks)
+template <int NB>
+__global__ __launch_bounds__(64) void ascent_i8_batched(const AscArgs *args, const int64_t *prefix, int count)
 {
-    switch (nb) {
-    case 1: hipLaunchKernelGGL(ascent_i8_kernel<1>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(ascent_i8_kernel<2>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 3: hipLaunchKernelGGL(ascent_i8_kernel<3>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(ascent_i8_kernel<4>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 5: hipLaunchKernelGGL(ascent_i8_kernel<5>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 6: hipLaunchKernelGGL(ascent_i8_kernel<6>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 7: hipLaunchKernelGGL(ascent_i8_kernel<7>, dim3(blocks), dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL(ascent_i8_kernel<8>, dim3(blocks), dim3(256), 0, st, a); break;
-    }
-    return hipGetLastError();
+    const int i = ubqp_find_inst(prefix, count, blockIdx.x);
+    const AscArgs a = args[i];
+    const int64_t w0 = blockIdx.x - prefix[i], nw = prefix[i + 1] - prefix[i];
+    int64_t P = *a.nidx_d - a.offset;
+    P = P < a.max_idx ? P : a.max_idx;
+    for (int64_t p = w0; p < P; p += nw) ascend_i8<NB>(a, p, threadIdx.x);
 }
+
+#define UBQP_NB_SWITCH(nb, LAUNCH) \
+    switch (nb) {                    \
+    case 1: LAUNCH(1); break;        \
+    case 2: LAUNCH(2); break;        \
+    case 3: LAUNCH(3); break;        \
+    case 4: LAUNCH(4); break;        \
+    case 5: LAUNCH(5); break;        \
+    case 6: LAUNCH(6); break;        \
+    case 7: LAUNCH(7); break;        \
+    default: LAUNCH(8); break;       \
+    }
 
 }  // namespace
 
-hipError_t ubqp_launch_ascent(hipStream_t st, const ubqp_problem *p, uint64_t *X, int64_t x_rows, const int32_t *idx,
-                              const int64_t *nidx_d, int64_t offset, int64_t max_idx, const int32_t *Y, int64_t *f,
-                              int32_t max_flips, int32_t *flips, int32_t *err_flag)
+AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, const int32_t *idx, const int64_t *nidx_d,
+                         int64_t offset, int64_t cap, const int32_t *Y, int64_t *f, int32_t max_flips, int32_t *flips,
+                         int32_t *err_flag)
 {
     AscArgs a{};
     a.qa = p->qa;
@@ -456,17 +440,46 @@ hipError_t ubqp_launch_ascent(hipStream_t st, const ubqp_problem *p, uint64_t *X
     a.idx = idx;
     a.nidx_d = nidx_d;
     a.offset = offset;
-    a.max_idx = max_idx;
+    a.max_idx = cap;
     a.Y = Y;
     a.f = f;
     a.flips = flips;
     a.max_flips = max_flips;
     a.safety_cap = 64 * p->n_pad + 4096;
     a.err = err_flag;
-    const int nb = (p->n_pad + 1023) / 1024;
-    int64_t blocks = (max_idx + 3) / 4;
-    if (blocks > 2048) blocks = 2048;
-    if (blocks < 1) blocks = 1;
-    if (p->planes == 2) return launch_nb<int16_t>(st, a, nb, (unsigned)blocks);
-    return launch_i8(st, a, nb, (unsigned)blocks);
+    return a;
+}
+
+int ubqp_ascent_nb(const AscArgs &a) { return (a.n_pad + 1023) / 1024; }
+int64_t ubqp_ascent_waves(const AscArgs &a) { return a.max_idx < 8192 ? (a.max_idx < 1 ? 1 : a.max_idx) : 8192; }
+
+hipError_t ubqp_launch_ascent(hipStream_t st, const AscArgs &a)
+{
+    const unsigned waves = (unsigned)ubqp_ascent_waves(a);
+#define L16(NB) hipLaunchKernelGGL((ascent_kernel<NB, int16_t>), dim3(waves), dim3(64), 0, st, a)
+#define L8(NB) hipLaunchKernelGGL(ascent_i8_kernel<NB>, dim3(waves), dim3(64), 0, st, a)
+    if (a.planes == 2) {
+        UBQP_NB_SWITCH(ubqp_ascent_nb(a), L16)
+    } else {
+        UBQP_NB_SWITCH(ubqp_ascent_nb(a), L8)
+    }
+#undef L16
+#undef L8
+    return hipGetLastError();
+}
+
+hipError_t ubqp_launch_ascent_batch(hipStream_t st, int planes, int nb, const AscArgs *args, const int64_t *prefix,
+                                    int count, int64_t waves)
+{
+    if (waves <= 0) return hipSuccess;
+#define L16(NB) hipLaunchKernelGGL((ascent_batched<NB, int16_t>), dim3((unsigned)waves), dim3(64), 0, st, args, prefix, count)
+#define L8(NB) hipLaunchKernelGGL(ascent_i8_batched<NB>, dim3((unsigned)waves), dim3(64), 0, st, args, prefix, count)
+    if (planes == 2) {
+        UBQP_NB_SWITCH(nb, L16)
+    } else {
+        UBQP_NB_SWITCH(nb, L8)
+    }
+#undef L16
+#undef L8
+    return hipGetLastError();
 }

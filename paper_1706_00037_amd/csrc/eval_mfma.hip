@@ -56,24 +56,6 @@ __device__ inline int32_t row16_sum(int32_t v)
     return v;
 }
 
-struct EvalArgs {
-    const int8_t *q;        // plane 0; plane p at q + p * plane_stride
-    int64_t plane_stride;
-    int32_t n_pad;
-    const uint64_t *X;
-    int32_t W;
-    int64_t M;              // rows (or capacity of the gather list)
-    const int32_t *rows;    // gather list (STORE_Y) or null, already offset to the chunk
-    int64_t x_rows;         // rows of X (gather targets outside [0, x_rows) read as zero)
-    const int64_t *nrows_d; // device length of the whole list (STORE_Y)
-    int64_t offset;         // first list entry of this chunk
-    int64_t *f;             // row-dot output
-    int32_t *Y;             // Y output [planes][M][n_pad]
-    int64_t weight0;        // weight of plane 0 in the row dot
-    int32_t m_tiles, n_tiles;
-    const int32_t *diag;    // KEYS: q_jj
-    int32_t keys_pl;        // KEYS: columns per lane of the ascent (16 NB)
-};
 
 // Epilogues of the contraction.
 enum { EPI_ROWDOT = 0, EPI_Y = 1, EPI_KEYS = 2 };
@@ -83,8 +65,18 @@ enum { EPI_ROWDOT = 0, EPI_Y = 1, EPI_KEYS = 2 };
 #define SG_MFMA 0x008
 #define SG_DSR 0x100
 
+// Consecutive workgroups go round-robin to the 8 XCDs: give each XCD a
+// contiguous run of tiles, a bijection on [0, total).  Tiles are numbered
+// n-tile-major, so the workgroups resident on one XCD share a Q column block in
+// its L2.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t total)
+{
+    const int64_t xcd = b % 8, j = b / 8, per = total / 8, rem = total % 8;
+    return xcd * per + (xcd < rem ? xcd : rem) + j;
+}
+
 template <int EPI, int KC>
-__global__ __launch_bounds__(THR, KC == 128 ? 2 : 1) void eval_kernel(EvalArgs a)
+__device__ void eval_body(const EvalArgs &a, int64_t tile)
 {
     constexpr bool STORE_Y = EPI != EPI_ROWDOT;
     constexpr int BPITCH = KC + 16;       // bytes per staged Q row (16-byte skew: conflict-free reads)
@@ -96,18 +88,10 @@ __global__ __launch_bounds__(THR, KC == 128 ? 2 : 1) void eval_kernel(EvalArgs a
     __shared__ __align__(16) uint64_t As[2][BM * APITCH];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    // XCD-aware tile order: consecutive workgroups go round-robin to the 8 XCDs;
-    // give each XCD a contiguous run of tiles, ordered n-tile-major so the
-    // workgroups resident on one XCD share the same Q column block in its L2.
     const int64_t T = (int64_t)a.m_tiles * a.n_tiles;
-    const int64_t b = blockIdx.x;
-    const int64_t xcd = b % 8, j = b / 8, per = T / 8, rem = T % 8;
-    // XCD x gets tiles [start_x, start_x + per + (x < rem)), a bijection on [0, T)
-    const int64_t t = xcd * per + (xcd < rem ? xcd : rem) + j;
-    if (b >= T) return;
+    const int plane = (int)(tile / T);
+    const int64_t t = tile - plane * T;
     const int nt = (int)(t / a.m_tiles), mt = (int)(t % a.m_tiles);
-    const int plane = blockIdx.y;
 
     int64_t Mrows = a.M;
     if (STORE_Y) { const int64_t k = *a.nrows_d - a.offset; Mrows = k < a.M ? k : a.M; }
@@ -297,69 +281,132 @@ __global__ __launch_bounds__(THR, KC == 128 ? 2 : 1) void eval_kernel(EvalArgs a
     }
 }
 
-// f[c] = bias * popcount(X_c)^2 (the constant part of the split planes) or 0.
-__global__ __launch_bounds__(256) void eval_init(const uint64_t *__restrict__ X, int32_t W, int64_t M, int64_t bias,
-                                                 int64_t *__restrict__ f)
+template <int EPI, int KC>
+__global__ __launch_bounds__(THR, KC == 128 ? 2 : 1) void eval_kernel(EvalArgs a, int64_t total)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= M) return;
+    eval_body<EPI, KC>(a, xcd_tile(blockIdx.x, total));
+}
+
+template <int EPI, int KC>
+__global__ __launch_bounds__(THR, KC == 128 ? 2 : 1) void eval_batched(const EvalArgs *args, const int64_t *prefix,
+                                                                      int count, int64_t total)
+{
+    const int64_t t = xcd_tile(blockIdx.x, total);
+    const int i = ubqp_find_inst(prefix, count, t);
+    eval_body<EPI, KC>(args[i], t - prefix[i]);
+}
+
+// f[c] = bias * popcount(X_c)^2 (the constant part of the split planes) or 0.
+__device__ void eval_init_body(const EvalArgs &a, int64_t bid)
+{
+    const int64_t c = bid * 256 + threadIdx.x;
+    if (c >= a.M) return;
     int64_t v = 0;
-    if (bias) {
+    if (a.bias) {
         int64_t k = 0;
-        for (int w = 0; w < W; w++) k += __popcll(X[c * W + w]);
-        v = bias * k * k;
+        for (int w = 0; w < a.W; w++) k += __popcll(a.X[c * a.W + w]);
+        v = a.bias * k * k;
     }
-    f[c] = v;
+    a.f[c] = v;
+}
+
+__global__ __launch_bounds__(256) void eval_init(EvalArgs a) { eval_init_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void eval_init_batched(const EvalArgs *args, const int64_t *prefix, int count)
+{
+    const int i = ubqp_find_inst(prefix, count, blockIdx.x);
+    eval_init_body(args[i], blockIdx.x - prefix[i]);
 }
 
 #ifndef EVAL_KC
 #define EVAL_KC 128
 #endif
 
-EvalArgs make_args(const ubqp_problem *p, const uint64_t *X, int64_t M)
+}  // namespace
+
+EvalArgs ubqp_eval_args(const ubqp_problem *p, const uint64_t *X, int64_t M, int64_t *f)
 {
     EvalArgs a{};
     a.q = p->q;
     a.plane_stride = (int64_t)p->n_pad * p->n_pad;
     a.n_pad = p->n_pad;
+    a.planes = p->planes;
     a.X = X;
     a.W = p->W;
     a.M = M;
-    a.weight0 = p->weight0;
     a.x_rows = M;
+    a.f = f;
+    a.weight0 = p->weight0;
+    a.bias = p->bias;
     a.m_tiles = (int32_t)((M + BM - 1) / BM);
     a.n_tiles = p->n_pad / BN;
     return a;
 }
 
-}  // namespace
-
-hipError_t ubqp_launch_eval(hipStream_t st, const ubqp_problem *p, const uint64_t *X, int64_t M, int64_t *f)
+EvalArgs ubqp_yrows_args(const ubqp_problem *p, const uint64_t *X, int64_t x_rows, const int32_t *rows,
+                         const int64_t *nrows_d, int64_t offset, int64_t cap, int32_t *Y)
 {
-    hipLaunchKernelGGL(eval_init, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, X, p->W, M, p->bias, f);
-    EvalArgs a = make_args(p, X, M);
-    a.f = f;
-    const int64_t T = (int64_t)a.m_tiles * a.n_tiles;
-    hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, EVAL_KC>), dim3((unsigned)T, p->planes), dim3(THR), 0, st, a);
+    EvalArgs a = ubqp_eval_args(p, X, cap, nullptr);
+    a.x_rows = x_rows;
+    a.rows = rows + offset;
+    a.nrows_d = nrows_d;
+    a.offset = offset;
+    a.Y = Y;
+    a.diag = p->diag;
+    a.keys_pl = p->ncol_a / 64;
+    return a;
+}
+
+int64_t ubqp_eval_tiles(const EvalArgs &a) { return (int64_t)a.m_tiles * a.n_tiles * a.planes; }
+int64_t ubqp_yrows_tiles(const EvalArgs &a)
+{
+    return (int64_t)a.m_tiles * a.n_tiles * (a.planes == 1 ? 1 : a.planes);
+}
+int64_t ubqp_eval_init_blocks(const EvalArgs &a) { return (a.M + 255) / 256; }
+
+hipError_t ubqp_launch_eval(hipStream_t st, const EvalArgs &a)
+{
+    hipLaunchKernelGGL(eval_init, dim3((unsigned)ubqp_eval_init_blocks(a)), dim3(256), 0, st, a);
+    const int64_t T = ubqp_eval_tiles(a);
+    hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, EVAL_KC>), dim3((unsigned)T), dim3(THR), 0, st, a, T);
     return hipGetLastError();
 }
 
-hipError_t ubqp_launch_yrows(hipStream_t st, const ubqp_problem *p, const uint64_t *X, int64_t x_rows,
-                             const int32_t *rows, const int64_t *nrows_d, int64_t offset, int64_t cap, int32_t *Y)
+hipError_t ubqp_launch_yrows(hipStream_t st, const EvalArgs &a)
 {
-    EvalArgs a = make_args(p, X, cap);
-    a.x_rows = x_rows;
-    a.rows = rows + offset;
-    a.offset = offset;
-    a.nrows_d = nrows_d;
-    a.Y = Y;
-    const int64_t T = (int64_t)a.m_tiles * a.n_tiles;
-    if (p->planes == 1) {
-        a.diag = p->diag;
-        a.keys_pl = p->ncol_a / 64;
-        hipLaunchKernelGGL((eval_kernel<EPI_KEYS, EVAL_KC>), dim3((unsigned)T, 1), dim3(THR), 0, st, a);
-    } else {
-        hipLaunchKernelGGL((eval_kernel<EPI_Y, EVAL_KC>), dim3((unsigned)T, p->planes), dim3(THR), 0, st, a);
+    const int64_t T = ubqp_yrows_tiles(a);
+    if (a.planes == 1)
+        hipLaunchKernelGGL((eval_kernel<EPI_KEYS, EVAL_KC>), dim3((unsigned)T), dim3(THR), 0, st, a, T);
+    else
+        hipLaunchKernelGGL((eval_kernel<EPI_Y, EVAL_KC>), dim3((unsigned)T), dim3(THR), 0, st, a, T);
+    return hipGetLastError();
+}
+
+hipError_t ubqp_launch_eval_init_batch(hipStream_t st, const EvalArgs *args, const int64_t *prefix, int count,
+                                       int64_t blocks)
+{
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eval_init_batched, dim3((unsigned)blocks), dim3(256), 0, st, args, prefix, count);
+    return hipGetLastError();
+}
+
+hipError_t ubqp_launch_eval_batch(hipStream_t st, int epilogue, const EvalArgs *args, const int64_t *prefix,
+                                  int count, int64_t tiles)
+{
+    if (tiles <= 0) return hipSuccess;
+    switch (epilogue) {
+    case EPI_ROWDOT:
+        hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, EVAL_KC>), dim3((unsigned)tiles), dim3(THR), 0, st, args, prefix,
+                           count, tiles);
+        break;
+    case EPI_Y:
+        hipLaunchKernelGGL((eval_batched<EPI_Y, EVAL_KC>), dim3((unsigned)tiles), dim3(THR), 0, st, args, prefix,
+                           count, tiles);
+        break;
+    default:
+        hipLaunchKernelGGL((eval_batched<EPI_KEYS, EVAL_KC>), dim3((unsigned)tiles), dim3(THR), 0, st, args, prefix,
+                           count, tiles);
+        break;
     }
     return hipGetLastError();
 }

@@ -43,75 +43,65 @@ __device__ void block_sum_max(int64_t &s, int64_t &m)
     __syncthreads();
 }
 
-__device__ inline bool passes(int64_t f, int64_t M, int32_t num, int32_t den, __int128 rhs)
-{
-    return (__int128)den * M * f > rhs;
-}
+__device__ inline bool passes(int64_t f, int64_t M, int32_t den, __int128 rhs) { return (__int128)den * M * f > rhs; }
 
-__global__ __launch_bounds__(THR) void screen_reduce(const int64_t *__restrict__ f, int64_t M,
-                                                     int64_t *__restrict__ psum, int64_t *__restrict__ pmax)
+__device__ void reduce_body(const ScreenArgs &a, int64_t bid)
 {
-    const int64_t base = blockIdx.x * CH;
+    const int64_t base = bid * CH;
     int64_t s = 0, m = INT64_MIN;
 #pragma unroll
     for (int i = 0; i < PER; i++) {
         const int64_t c = base + i * THR + threadIdx.x;
-        if (c < M) { const int64_t v = f[c]; s += v; m = v > m ? v : m; }
+        if (c < a.M) { const int64_t v = a.f[c]; s += v; m = v > m ? v : m; }
     }
     block_sum_max(s, m);
-    if (threadIdx.x == 0) { psum[blockIdx.x] = s; pmax[blockIdx.x] = m; }
+    if (threadIdx.x == 0) { a.psum[bid] = s; a.pmax[bid] = m; }
 }
 
 // Sum and Max of the whole population from the block partials.
-__device__ void total_sum_max(const int64_t *psum, const int64_t *pmax, int nblk, int64_t &s, int64_t &m)
+__device__ void total_sum_max(const ScreenArgs &a, int64_t &s, int64_t &m)
 {
     s = 0;
     m = INT64_MIN;
-    for (int b = threadIdx.x; b < nblk; b += THR) { s += psum[b]; m = pmax[b] > m ? pmax[b] : m; }
+    for (int b = threadIdx.x; b < a.nblk; b += THR) { s += a.psum[b]; m = a.pmax[b] > m ? a.pmax[b] : m; }
     block_sum_max(s, m);
 }
 
-__global__ __launch_bounds__(THR) void screen_count(const int64_t *__restrict__ f, int64_t M, int32_t num,
-                                                    int32_t den, const int64_t *__restrict__ psum,
-                                                    const int64_t *__restrict__ pmax, int nblk,
-                                                    int64_t *__restrict__ cnt, int64_t *__restrict__ sum_max)
+__device__ void count_body(const ScreenArgs &a, int64_t bid)
 {
     int64_t S, Mx;
-    total_sum_max(psum, pmax, nblk, S, Mx);
-    const __int128 rhs = (__int128)(den - num) * S + (__int128)num * M * Mx;
-    const int64_t base = blockIdx.x * CH;
+    total_sum_max(a, S, Mx);
+    const __int128 rhs = (__int128)(a.lam_den - a.lam_num) * S + (__int128)a.lam_num * a.M * Mx;
+    const int64_t base = bid * CH;
     int64_t k = 0;
 #pragma unroll
     for (int i = 0; i < PER; i++) {
         const int64_t c = base + i * THR + threadIdx.x;
-        if (c < M && passes(f[c], M, num, den, rhs)) k++;
+        if (c < a.M && passes(a.f[c], a.M, a.lam_den, rhs)) k++;
     }
     int64_t dummy = 0;
     block_sum_max(k, dummy);
     if (threadIdx.x == 0) {
-        cnt[blockIdx.x] = k;
-        if (blockIdx.x == 0) { sum_max[0] = S; sum_max[1] = Mx; }
+        a.cnt[bid] = k;
+        if (bid == 0) { a.sum_max[0] = S; a.sum_max[1] = Mx; }
     }
 }
 
-__global__ __launch_bounds__(THR) void screen_scatter(const int64_t *__restrict__ f, int64_t M, int32_t num,
-                                                      int32_t den, const int64_t *__restrict__ cnt, int nblk,
-                                                      const int64_t *__restrict__ sum_max,
-                                                      int32_t *__restrict__ idx, int64_t *__restrict__ npass)
+__device__ void scatter_body(const ScreenArgs &a, int64_t bid)
 {
     __shared__ int64_t wtot[THR / 64];
     // passers in earlier blocks
     int64_t off = 0, dummy = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += THR) off += cnt[b];
+    for (int b = threadIdx.x; b < (int)bid; b += THR) off += a.cnt[b];
     block_sum_max(off, dummy);
-    const __int128 rhs = (__int128)(den - num) * sum_max[0] + (__int128)num * M * sum_max[1];
+    const __int128 rhs = (__int128)(a.lam_den - a.lam_num) * a.sum_max[0] + (__int128)a.lam_num * a.M * a.sum_max[1];
     // each thread owns PER consecutive candidates, so thread order is index order
-    const int64_t c0 = blockIdx.x * CH + (int64_t)threadIdx.x * PER;
+    const int64_t c0 = bid * CH + (int64_t)threadIdx.x * PER;
     uint32_t bits = 0;
 #pragma unroll
     for (int i = 0; i < PER; i++) {
         const int64_t c = c0 + i;
-        if (c < M && passes(f[c], M, num, den, rhs)) bits |= 1u << i;
+        if (c < a.M && passes(a.f[c], a.M, a.lam_den, rhs)) bits |= 1u << i;
     }
     const int mine = __popc(bits);
     // exclusive scan of `mine` over the block
@@ -126,23 +116,67 @@ __global__ __launch_bounds__(THR) void screen_scatter(const int64_t *__restrict_
     int64_t pos = off + incl - mine;
     for (int i = 0; i < wv; i++) pos += wtot[i];
     for (int i = 0; i < PER; i++)
-        if (bits & (1u << i)) idx[pos++] = (int32_t)(c0 + i);
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == THR - 1) *npass = pos;
+        if (bits & (1u << i)) a.idx[pos++] = (int32_t)(c0 + i);
+    if (bid == a.nblk - 1 && threadIdx.x == THR - 1) *a.npass = pos;
+}
+
+__global__ __launch_bounds__(THR) void screen_reduce(ScreenArgs a) { reduce_body(a, blockIdx.x); }
+__global__ __launch_bounds__(THR) void screen_count(ScreenArgs a) { count_body(a, blockIdx.x); }
+__global__ __launch_bounds__(THR) void screen_scatter(ScreenArgs a) { scatter_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(THR) void screen_reduce_b(const ScreenArgs *args, const int64_t *prefix, int count)
+{
+    const int i = ubqp_find_inst(prefix, count, blockIdx.x);
+    reduce_body(args[i], blockIdx.x - prefix[i]);
+}
+__global__ __launch_bounds__(THR) void screen_count_b(const ScreenArgs *args, const int64_t *prefix, int count)
+{
+    const int i = ubqp_find_inst(prefix, count, blockIdx.x);
+    count_body(args[i], blockIdx.x - prefix[i]);
+}
+__global__ __launch_bounds__(THR) void screen_scatter_b(const ScreenArgs *args, const int64_t *prefix, int count)
+{
+    const int i = ubqp_find_inst(prefix, count, blockIdx.x);
+    scatter_body(args[i], blockIdx.x - prefix[i]);
 }
 
 }  // namespace
 
-size_t ubqp_screen_partials_bytes(int64_t M) { return (size_t)((M + CH - 1) / CH) * 3 * sizeof(int64_t); }
+int32_t ubqp_screen_blocks(int64_t M) { return (int32_t)((M + CH - 1) / CH); }
+size_t ubqp_screen_partials_bytes(int64_t M) { return (size_t)ubqp_screen_blocks(M) * 3 * sizeof(int64_t); }
 
-hipError_t ubqp_launch_screen(hipStream_t st, const int64_t *f, int64_t M, int32_t lam_num, int32_t lam_den,
-                              int32_t *idx, int64_t *npass, int64_t *sum_max, void *partials)
+ScreenArgs ubqp_screen_args(const int64_t *f, int64_t M, int32_t lam_num, int32_t lam_den, int32_t *idx,
+                            int64_t *npass, int64_t *sum_max, void *partials)
 {
-    const int nblk = (int)((M + CH - 1) / CH);
-    int64_t *psum = (int64_t *)partials, *pmax = psum + nblk, *cnt = pmax + nblk;
-    hipLaunchKernelGGL(screen_reduce, dim3(nblk), dim3(THR), 0, st, f, M, psum, pmax);
-    hipLaunchKernelGGL(screen_count, dim3(nblk), dim3(THR), 0, st, f, M, lam_num, lam_den, psum, pmax, nblk, cnt,
-                       sum_max);
-    hipLaunchKernelGGL(screen_scatter, dim3(nblk), dim3(THR), 0, st, f, M, lam_num, lam_den, cnt, nblk, sum_max,
-                       idx, npass);
+    ScreenArgs a{};
+    a.f = f;
+    a.M = M;
+    a.lam_num = lam_num;
+    a.lam_den = lam_den;
+    a.idx = idx;
+    a.npass = npass;
+    a.sum_max = sum_max;
+    a.nblk = ubqp_screen_blocks(M);
+    a.psum = (int64_t *)partials;
+    a.pmax = a.psum + a.nblk;
+    a.cnt = a.pmax + a.nblk;
+    return a;
+}
+
+hipError_t ubqp_launch_screen(hipStream_t st, const ScreenArgs &a)
+{
+    hipLaunchKernelGGL(screen_reduce, dim3(a.nblk), dim3(THR), 0, st, a);
+    hipLaunchKernelGGL(screen_count, dim3(a.nblk), dim3(THR), 0, st, a);
+    hipLaunchKernelGGL(screen_scatter, dim3(a.nblk), dim3(THR), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t ubqp_launch_screen_batch(hipStream_t st, const ScreenArgs *args, const int64_t *prefix, int count,
+                                    int64_t blocks)
+{
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(screen_reduce_b, dim3((unsigned)blocks), dim3(THR), 0, st, args, prefix, count);
+    hipLaunchKernelGGL(screen_count_b, dim3((unsigned)blocks), dim3(THR), 0, st, args, prefix, count);
+    hipLaunchKernelGGL(screen_scatter_b, dim3((unsigned)blocks), dim3(THR), 0, st, args, prefix, count);
     return hipGetLastError();
 }

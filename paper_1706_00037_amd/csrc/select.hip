@@ -8,9 +8,15 @@
 // Random solutions are SplitMix64 (Steele, Lea & Flood 2014) used as a counter
 // generator: word w of seed slot s in generation g is output (g S + s) W + w of
 // the generator seeded with run_seed.
+//
+// The generation index lives on the device (ubqp_scal::gen, advanced by the
+// last kernel of a generation), so the launches of a generation do not depend
+// on it and can be replayed as a graph.
 #include "ubqp_internal.h"
 
 namespace {
+
+constexpr int THR = 256;
 
 __device__ inline uint64_t splitmix_output(uint64_t seed, uint64_t i)
 {
@@ -29,37 +35,42 @@ __device__ inline uint64_t random_word(uint64_t run_seed, int64_t g, int64_t S, 
     return v;
 }
 
-__global__ __launch_bounds__(256) void seed_init_kernel(uint64_t *seeds, int64_t S, int32_t n, int32_t W,
-                                                        uint64_t run_seed, const uint64_t *deriv_x,
-                                                        ubqp_scal *scal)
+__device__ void seed_init_body(const SelArgs &a, int64_t bid)
 {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t id = bid * THR + threadIdx.x;
     if (id == 0) {
-        scal->have_best = 0;
-        scal->best_f = INT64_MIN;
-        scal->best_c = -1;
+        a.scal->have_best = 0;
+        a.scal->best_f = INT64_MIN;
+        a.scal->best_c = -1;
+        a.scal->gen = 0;
     }
-    if (id >= S * W) return;
-    const int64_t s = id / W;
-    const int32_t w = (int32_t)(id - s * W);
-    seeds[id] = (s == 0 && deriv_x) ? deriv_x[w] : random_word(run_seed, 0, S, s, W, w, n);
+    if (id >= a.S * a.W) return;
+    const int64_t s = id / a.W;
+    const int32_t w = (int32_t)(id - s * a.W);
+    a.seeds[id] = (s == 0 && a.deriv_x) ? a.deriv_x[w] : random_word(a.run_seed, 0, a.S, s, a.W, w, a.n);
 }
 
-// One block: incumbent update and statistics of generation g.
-__global__ __launch_bounds__(256) void incumbent_kernel(const uint64_t *X, int32_t W, const int64_t *f,
-                                                        const int32_t *flips, const int32_t *idx, ubqp_scal *scal,
-                                                        uint64_t *best_x, int64_t *stats, int32_t g)
+// f before ascent into row `gen` of the dump.
+__device__ void dump_body(const SelArgs &a, int64_t bid)
 {
-    __shared__ int64_t sf[4], sfl[4];
-    __shared__ int32_t sc[4];
+    const int64_t c = bid * THR + threadIdx.x;
+    if (a.f_dump && c < a.M) a.f_dump[(int64_t)a.scal->gen * a.M + c] = a.f[c];
+}
+
+// One block: incumbent update and statistics of the current generation.
+__device__ void incumbent_body(const SelArgs &a)
+{
+    __shared__ int64_t sf[THR / 64], sfl[THR / 64];
+    __shared__ int32_t sc[THR / 64];
     __shared__ int32_t winner;
+    ubqp_scal *scal = a.scal;
     const int64_t P = scal->npass;
     int64_t bf = INT64_MIN, fl = 0;
     int32_t bc = 0x7FFFFFFF;
-    for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
-        const int32_t c = idx[p];
-        const int64_t v = f[c];
-        fl += flips[c];
+    for (int64_t p = threadIdx.x; p < P; p += THR) {
+        const int32_t c = a.idx[p];
+        const int64_t v = a.f[c];
+        fl += a.flips[c];
         if (v > bf || (v == bf && c < bc)) { bf = v; bc = c; }
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -73,7 +84,7 @@ __global__ __launch_bounds__(256) void incumbent_kernel(const uint64_t *X, int32
     __syncthreads();
     if (threadIdx.x == 0) {
         bf = sf[0]; bc = sc[0]; fl = sfl[0];
-        for (int i = 1; i < 4; i++) {
+        for (int i = 1; i < THR / 64; i++) {
             fl += sfl[i];
             if (sf[i] > bf || (sf[i] == bf && sc[i] < bc)) { bf = sf[i]; bc = sc[i]; }
         }
@@ -84,7 +95,7 @@ __global__ __launch_bounds__(256) void incumbent_kernel(const uint64_t *X, int32
             scal->best_c = bc;
             winner = bc;
         }
-        int64_t *st = stats + (int64_t)g * 5;
+        int64_t *st = a.stats + (int64_t)scal->gen * 5;
         st[0] = scal->sum_max[0];
         st[1] = scal->sum_max[1];
         st[2] = P;
@@ -93,75 +104,131 @@ __global__ __launch_bounds__(256) void incumbent_kernel(const uint64_t *X, int32
     }
     __syncthreads();
     if (winner >= 0)
-        for (int w = threadIdx.x; w < W; w += blockDim.x) best_x[w] = X[(int64_t)winner * W + w];
+        for (int w = threadIdx.x; w < a.W; w += THR) a.best_x[w] = a.X[(int64_t)winner * a.W + w];
 }
 
 // Rank of each passer by (f desc, index asc); the top S-1 become seeds 1..S-1.
-__global__ __launch_bounds__(256) void rank_kernel(const uint64_t *X, int32_t W, const int64_t *f,
-                                                   const int32_t *idx, const ubqp_scal *scal, int64_t S,
-                                                   uint64_t *seeds)
+__device__ void rank_body(const SelArgs &a, int64_t bid)
 {
-    __shared__ int64_t tf[256];
-    const int64_t P = scal->npass;
-    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x;
+    __shared__ int64_t tf[THR];
+    const int64_t P = a.scal->npass;
+    const int64_t p0 = bid * THR;
     if (p0 >= P) return;
     const int64_t p = p0 + threadIdx.x;
-    const int64_t fp = p < P ? f[idx[p]] : 0;
+    const int64_t fp = p < P ? a.f[a.idx[p]] : 0;
     int64_t r = 0;
-    for (int64_t base = 0; base < P; base += 256) {
+    for (int64_t base = 0; base < P; base += THR) {
         __syncthreads();
-        if (base + threadIdx.x < P) tf[threadIdx.x] = f[idx[base + threadIdx.x]];
+        if (base + threadIdx.x < P) tf[threadIdx.x] = a.f[a.idx[base + threadIdx.x]];
         __syncthreads();
-        const int64_t lim = P - base < 256 ? P - base : 256;
+        const int64_t lim = P - base < THR ? P - base : THR;
         for (int64_t q = 0; q < lim; q++) {
             const int64_t fq = tf[q];
             r += (fq > fp) || (fq == fp && base + q < p);
         }
     }
-    if (p < P && r < S - 1) {
-        const uint64_t *src = X + (int64_t)idx[p] * W;
-        uint64_t *dst = seeds + (1 + r) * W;
-        for (int w = 0; w < W; w++) dst[w] = src[w];
+    if (p < P && r < a.S - 1) {
+        const uint64_t *src = a.X + (int64_t)a.idx[p] * a.W;
+        uint64_t *dst = a.seeds + (1 + r) * a.W;
+        for (int w = 0; w < a.W; w++) dst[w] = src[w];
     }
 }
 
 // Seed 0 (incumbent, or random while none exists) and the random tail slots.
-__global__ __launch_bounds__(256) void seed_fill_kernel(uint64_t *seeds, int64_t S, int32_t n, int32_t W,
-                                                        uint64_t run_seed, int32_t g_next, const ubqp_scal *scal,
-                                                        const uint64_t *best_x)
+__device__ void seed_fill_body(const SelArgs &a, int64_t bid)
 {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= S * W) return;
-    const int64_t s = id / W;
-    const int32_t w = (int32_t)(id - s * W);
-    const int64_t P = scal->npass;
-    const int64_t ranked = P < S - 1 ? P : S - 1;
+    const int64_t id = bid * THR + threadIdx.x;
+    if (id >= a.S * a.W) return;
+    const int64_t s = id / a.W;
+    const int32_t w = (int32_t)(id - s * a.W);
+    const int64_t P = a.scal->npass;
+    const int64_t ranked = P < a.S - 1 ? P : a.S - 1;
+    const int32_t g_next = a.scal->gen + 1;
     if (s == 0)
-        seeds[id] = scal->have_best ? best_x[w] : random_word(run_seed, g_next, S, 0, W, w, n);
+        a.seeds[id] = a.scal->have_best ? a.best_x[w] : random_word(a.run_seed, g_next, a.S, 0, a.W, w, a.n);
     else if (s >= 1 + ranked)
-        seeds[id] = random_word(run_seed, g_next, S, s, W, w, n);
+        a.seeds[id] = random_word(a.run_seed, g_next, a.S, s, a.W, w, a.n);
+}
+
+__global__ __launch_bounds__(THR) void seed_init_kernel(SelArgs a) { seed_init_body(a, blockIdx.x); }
+
+#define BATCHED(NAME, BODY)                                                                               \
+    __global__ __launch_bounds__(THR) void NAME(const SelArgs *args, const int64_t *prefix, int count)  \
+    {                                                                                                     \
+        const int i = ubqp_find_inst(prefix, count, blockIdx.x);                                         \
+        BODY(args[i], blockIdx.x - prefix[i]);                                                            \
+    }
+BATCHED(seed_init_b, seed_init_body)
+BATCHED(dump_b, dump_body)
+BATCHED(rank_b, rank_body)
+BATCHED(seed_fill_b, seed_fill_body)
+#undef BATCHED
+
+__global__ __launch_bounds__(THR) void incumbent_b(const SelArgs *args, int count)
+{
+    incumbent_body(args[blockIdx.x]);
+}
+
+__global__ void advance_b(const SelArgs *args, int count)
+{
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i < count) args[i].scal->gen += 1;
 }
 
 }  // namespace
 
-hipError_t ubqp_launch_seed_init(hipStream_t st, uint64_t *seeds, int64_t S, int32_t n, uint64_t run_seed,
-                                 const uint64_t *deriv_x, ubqp_scal *scal)
+SelArgs ubqp_sel_args(int32_t n, int64_t M, int64_t S, uint64_t run_seed, const uint64_t *X, const int64_t *f,
+                      const int32_t *flips, const int32_t *idx, ubqp_scal *scal, uint64_t *best_x, uint64_t *seeds,
+                      int64_t *stats, const uint64_t *deriv_x, int64_t *f_dump)
 {
-    const int32_t W = (n + 63) / 64;
-    hipLaunchKernelGGL(seed_init_kernel, dim3((unsigned)((S * W + 255) / 256)), dim3(256), 0, st, seeds, S, n, W,
-                       run_seed, deriv_x, scal);
+    SelArgs a{};
+    a.n = n;
+    a.W = (n + 63) / 64;
+    a.M = M;
+    a.S = S;
+    a.run_seed = run_seed;
+    a.X = X;
+    a.f = f;
+    a.flips = flips;
+    a.idx = idx;
+    a.scal = scal;
+    a.best_x = best_x;
+    a.seeds = seeds;
+    a.stats = stats;
+    a.deriv_x = deriv_x;
+    a.f_dump = f_dump;
+    return a;
+}
+
+int64_t ubqp_seed_blocks(const SelArgs &a) { return (a.S * a.W + THR - 1) / THR; }
+int64_t ubqp_cand_blocks(const SelArgs &a) { return (a.M + THR - 1) / THR; }
+
+hipError_t ubqp_launch_seed_init(hipStream_t st, const SelArgs &a)
+{
+    hipLaunchKernelGGL(seed_init_kernel, dim3((unsigned)ubqp_seed_blocks(a)), dim3(THR), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t ubqp_launch_select(hipStream_t st, int32_t n, int64_t M, int64_t S, int32_t g, uint64_t run_seed,
-                              const uint64_t *X, const int64_t *f, const int32_t *flips, const int32_t *idx,
-                              ubqp_scal *scal, uint64_t *best_x, uint64_t *seeds, int64_t *stats)
+hipError_t ubqp_launch_seed_init_batch(hipStream_t st, const SelArgs *args, const int64_t *seed_prefix, int count,
+                                       int64_t seed_blocks)
 {
-    const int32_t W = (n + 63) / 64;
-    hipLaunchKernelGGL(incumbent_kernel, dim3(1), dim3(256), 0, st, X, W, f, flips, idx, scal, best_x, stats, g);
-    hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, X, W, f, idx, scal, S,
-                       seeds);
-    hipLaunchKernelGGL(seed_fill_kernel, dim3((unsigned)((S * W + 255) / 256)), dim3(256), 0, st, seeds, S, n, W,
-                       run_seed, g + 1, scal, best_x);
+    hipLaunchKernelGGL(seed_init_b, dim3((unsigned)seed_blocks), dim3(THR), 0, st, args, seed_prefix, count);
+    return hipGetLastError();
+}
+
+hipError_t ubqp_launch_dump_batch(hipStream_t st, const SelArgs *args, const int64_t *cand_prefix, int count,
+                                  int64_t cand_blocks)
+{
+    hipLaunchKernelGGL(dump_b, dim3((unsigned)cand_blocks), dim3(THR), 0, st, args, cand_prefix, count);
+    return hipGetLastError();
+}
+
+hipError_t ubqp_launch_select_batch(hipStream_t st, const SelArgs *args, const int64_t *cand_prefix,
+                                    int64_t cand_blocks, const int64_t *seed_prefix, int64_t seed_blocks, int count)
+{
+    hipLaunchKernelGGL(incumbent_b, dim3(count), dim3(THR), 0, st, args, count);
+    hipLaunchKernelGGL(rank_b, dim3((unsigned)cand_blocks), dim3(THR), 0, st, args, cand_prefix, count);
+    hipLaunchKernelGGL(seed_fill_b, dim3((unsigned)seed_blocks), dim3(THR), 0, st, args, seed_prefix, count);
+    hipLaunchKernelGGL(advance_b, dim3((count + 63) / 64), dim3(64), 0, st, args, count);
     return hipGetLastError();
 }

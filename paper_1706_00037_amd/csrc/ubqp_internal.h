@@ -20,7 +20,7 @@ struct ubqp_ctx {
     std::string err;
     // Growable device workspace of the step-level entry points, one buffer per slot
     // (a multi-start run owns its own device state).
-    enum Slot { WS_PARTIALS, WS_Y, WS_COUNT };
+    enum Slot { WS_PARTIALS, WS_Y, WS_STAGE, WS_COUNT };
     void *ws[WS_COUNT] = {};
     size_t ws_bytes[WS_COUNT] = {};
     int32_t *err_flag = nullptr;  // device int32: kernel-side checks (ascent safety cap)
@@ -28,6 +28,7 @@ struct ubqp_ctx {
 
 struct ubqp_problem {
     ubqp_ctx *ctx = nullptr;
+    void *mem = nullptr;       // owned device block holding the arrays below (null: a view into server memory)
     int32_t n = 0, n_pad = 0, W = 0, planes = 1;
     int8_t *q = nullptr;       // [planes][n_pad][n_pad]: plane 0 (hi or the only plane), plane 1 (lo)
     void *qa = nullptr;        // ascent matrix, zero diagonal: int8 [n_pad][ncol_a] (planes 1) or int16 [n_pad][n_pad]
@@ -38,37 +39,210 @@ struct ubqp_problem {
     int64_t bias = 0;          // 128 when split: f += bias * popcount(x)^2, y_i += bias * popcount(x)
 };
 
-// Small device scalars of a multistart run (WS_SCAL).
+// Small device scalars of a multistart run.
 struct ubqp_scal {
     int64_t npass;
     int64_t sum_max[2];
     int64_t best_f;
     int32_t have_best;
     int32_t best_c;
+    int32_t gen;       // generation being processed (advanced at the end of each generation)
+    int32_t pad_;
 };
 
-// ---- launchers (return hipGetLastError() of the launch) ----
-hipError_t ubqp_launch_diversify(hipStream_t st, int32_t n, const uint64_t *seeds, int64_t S, int32_t H,
-                                 uint64_t *X, int64_t M);
-// f[c] = X_c^T Q X_c for c < M.
-hipError_t ubqp_launch_eval(hipStream_t st, const ubqp_problem *p, const uint64_t *X, int64_t M, int64_t *f);
+// ---- error handling shared by abi.hip and plan.hip ----------------------------
+int ubqp_fail(ubqp_ctx *ctx, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int ubqp_hip_fail(ubqp_ctx *ctx, hipError_t e, const char *what);
+int ubqp_set_device(ubqp_ctx *ctx);
+int ubqp_check_flag(ubqp_ctx *ctx);  // read and clear the kernel-side error flag (synchronises)
+int ubqp_check_params(ubqp_ctx *ctx, const ubqp_problem *p, const ubqp_params *pr);
+// Make ctx->ws[slot] hold at least `bytes` (synchronises the stream when it grows).
+int ubqp_ws_ensure(ubqp_ctx *ctx, int slot, size_t bytes, void **out);
+
+#define UBQP_HIP_TRY(ctx, expr)                                         \
+    do {                                                                \
+        hipError_t e_ = (expr);                                         \
+        if (e_ != hipSuccess) return ubqp_hip_fail((ctx), e_, #expr);   \
+    } while (0)
+#define UBQP_TRY(expr)                 \
+    do {                               \
+        int r_ = (expr);               \
+        if (r_ != UBQP_OK) return r_;  \
+    } while (0)
+
+// Batched launches: a kernel covering several instances gets, per instance, its
+// argument struct and the number of blocks (or waves) it needs; block b of the
+// grid belongs to the instance i with prefix[i] <= b < prefix[i + 1].
+__device__ inline int ubqp_find_inst(const int64_t *prefix, int count, int64_t b)
+{
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---- resident problem construction (problem.hip) ------------------------------
+#define UBQP_CHECK_ASYM 1u   // some q_ij != q_ji
+#define UBQP_CHECK_RANGE 2u  // some q_ij outside [-32768, 32767]
+#define UBQP_CHECK_WIDE 4u   // some q_ij outside [-128, 127]
+struct ubqp_check_flags {
+    uint32_t bits;
+    uint32_t pad_;
+    unsigned long long first[2];  // smallest linear index of an asymmetric / out-of-range entry
+};
+// Sets n, n_pad, W, planes, weight0, bias, ncol_a (device pointers untouched).
+void ubqp_problem_geometry(ubqp_problem *p, int32_t n, int32_t planes);
+// Bytes of one block holding the planes, the ascent matrix, diag and deriv_x.
+size_t ubqp_problem_bytes(const ubqp_problem *p);
+// Points q, qa, diag and deriv_x into `mem` (ubqp_problem_bytes(p) bytes).
+void ubqp_problem_bind(ubqp_problem *p, char *mem);
+// Queue the check of the staged coefficients (elem bytes each, n x n) into *fl.
+hipError_t ubqp_queue_problem_check(hipStream_t st, const void *stage, int elem, int32_t n, ubqp_check_flags *fl);
+// Queue the build of p's resident arrays from the staged coefficients.
+hipError_t ubqp_queue_problem_build(hipStream_t st, const void *stage, int elem, const ubqp_problem *p);
+// Queue a fill of `words` 32-bit zeros.
+hipError_t ubqp_queue_zero(hipStream_t st, void *p, int64_t words);
+// UBQP_OK, or the error (with message) that the check flags report.
+int ubqp_check_verdict(ubqp_ctx *ctx, const ubqp_check_flags &fl, int32_t n);
+
+// ---- per-instance kernel arguments --------------------------------------------
+// Every kernel body takes one of these for its instance; single-instance
+// launches pass it by value, batched launches read it from a device array.
+
+struct DivArgs {             // Glover diversification
+    const uint64_t *seeds;
+    int32_t n, W, H;
+    uint64_t *X;
+    int64_t total;           // M * W output words
+};
+
+struct EvalArgs {            // int8 matrix-core contraction Y = X Q and its epilogues
+    const int8_t *q;         // plane 0; plane p at q + p * plane_stride
+    int64_t plane_stride;
+    int32_t n_pad;
+    int32_t planes;
+    const uint64_t *X;
+    int32_t W;
+    int64_t M;               // rows (or capacity of the gather list)
+    const int32_t *rows;     // gather list (Y / key epilogues), already offset to the chunk
+    int64_t x_rows;          // rows of X (gather targets outside [0, x_rows) read as zero)
+    const int64_t *nrows_d;  // device length of the whole list (Y / key epilogues)
+    int64_t offset;          // first list entry of this chunk
+    int64_t *f;              // row-dot output
+    int32_t *Y;              // Y output [planes][M][n_pad] or keys [M][n_pad]
+    int64_t weight0;         // weight of plane 0 in the row dot
+    int32_t m_tiles, n_tiles;
+    const int32_t *diag;     // keys: q_jj
+    int32_t keys_pl;         // keys: columns per lane of the ascent (16 NB)
+    int64_t bias;            // eval_init: f starts at bias * popcount(x)^2
+};
+
+struct ScreenArgs {          // exact T(lambda) screening
+    const int64_t *f;
+    int64_t M;
+    int32_t lam_num, lam_den;
+    int32_t *idx;
+    int64_t *npass, *sum_max;
+    int64_t *psum, *pmax, *cnt;  // partials, nblk each
+    int32_t nblk;
+};
+
+struct AscArgs {             // steepest 1-flip ascent
+    const void *qa;          // zero diagonal: int8 [n_pad][ncol_a] or int16 [n_pad][n_pad]
+    int32_t ncol_a;          // columns of the int8 ascent matrix (1024 NB)
+    const int32_t *diag;
+    int32_t n, n_pad, W, planes;
+    int64_t weight0, bias;
+    uint64_t *X;
+    int64_t x_rows;
+    const int32_t *idx;
+    const int64_t *nidx_d;   // length of the whole list
+    int64_t offset;          // first list entry of this chunk
+    int64_t max_idx;         // chunk capacity
+    const int32_t *Y;        // [planes][max_idx][n_pad] (keys for one plane), row r for entry offset + r
+    int64_t *f;
+    int32_t *flips;
+    int32_t max_flips, safety_cap;
+    int32_t *err;
+};
+
+struct SelArgs {             // incumbent update, next seeds, statistics, generation counter
+    int32_t n, W;
+    int64_t M, S;
+    uint64_t run_seed;
+    const uint64_t *X;
+    const int64_t *f;
+    const int32_t *flips;
+    const int32_t *idx;
+    ubqp_scal *scal;
+    uint64_t *best_x, *seeds;
+    int64_t *stats;
+    const uint64_t *deriv_x; // seed init: generation-0 seed 0 (or null)
+    int64_t *f_dump;         // optional: G x M objective dump
+};
+
+// ---- argument builders, grid sizes and launchers --------------------------------
+// Single-instance launchers take the arguments by value; *_batch launchers take a
+// device array of per-instance arguments and the block prefix (count + 1 entries).
+// Launchers return hipGetLastError() of the launch.
+
+#define UBQP_EPI_ROWDOT 0  // f += x . (x Q) (the batched objective)
+#define UBQP_EPI_Y 1       // store rows of x Q per plane (Delta initialisation, two planes)
+#define UBQP_EPI_KEYS 2    // store the ascent keys (Delta initialisation, one plane)
+
+int64_t ubqp_div_blocks(const DivArgs &a);
+hipError_t ubqp_launch_diversify(hipStream_t st, const DivArgs &a);
+hipError_t ubqp_launch_diversify_batch(hipStream_t st, const DivArgs *args, const int64_t *prefix, int count,
+                                       int64_t blocks);
+
+EvalArgs ubqp_eval_args(const ubqp_problem *p, const uint64_t *X, int64_t M, int64_t *f);
 // Chunk [offset, offset + cap) of a device-counted list: r < min(*nrows_d - offset, cap).
 // Two planes: Y[plane][r][:] = X_{rows[offset + r]} Q_plane; Y is [planes][cap][n_pad] int32.
 // One plane: Y[r][j] = the ascent key of column j (Delta_j * 256 + 2 (127 - j mod PL) + x_j).
 // Rows outside [0, x_rows) read as zero.
-hipError_t ubqp_launch_yrows(hipStream_t st, const ubqp_problem *p, const uint64_t *X, int64_t x_rows,
-                             const int32_t *rows, const int64_t *nrows_d, int64_t offset, int64_t cap, int32_t *Y);
+EvalArgs ubqp_yrows_args(const ubqp_problem *p, const uint64_t *X, int64_t x_rows, const int32_t *rows,
+                         const int64_t *nrows_d, int64_t offset, int64_t cap, int32_t *Y);
+int64_t ubqp_eval_tiles(const EvalArgs &a);
+int64_t ubqp_yrows_tiles(const EvalArgs &a);
+int64_t ubqp_eval_init_blocks(const EvalArgs &a);
+hipError_t ubqp_launch_eval(hipStream_t st, const EvalArgs &a);  // eval_init, then the row-dot contraction
+hipError_t ubqp_launch_yrows(hipStream_t st, const EvalArgs &a);
+hipError_t ubqp_launch_eval_init_batch(hipStream_t st, const EvalArgs *args, const int64_t *prefix, int count,
+                                       int64_t blocks);
+hipError_t ubqp_launch_eval_batch(hipStream_t st, int epilogue, const EvalArgs *args, const int64_t *prefix,
+                                  int count, int64_t tiles);
+
+int32_t ubqp_screen_blocks(int64_t M);
 size_t ubqp_screen_partials_bytes(int64_t M);
-hipError_t ubqp_launch_screen(hipStream_t st, const int64_t *f, int64_t M, int32_t lam_num, int32_t lam_den,
-                              int32_t *idx, int64_t *npass, int64_t *sum_max, void *partials);
+ScreenArgs ubqp_screen_args(const int64_t *f, int64_t M, int32_t lam_num, int32_t lam_den, int32_t *idx,
+                            int64_t *npass, int64_t *sum_max, void *partials);
+hipError_t ubqp_launch_screen(hipStream_t st, const ScreenArgs &a);
+hipError_t ubqp_launch_screen_batch(hipStream_t st, const ScreenArgs *args, const int64_t *prefix, int count,
+                                    int64_t blocks);
+
 // err_flag |= 1: safety cap reached; |= 2: an index outside [0, x_rows) was skipped.
 // Ascends X[idx[offset + r]] for r < min(*nidx_d - offset, cap), starting from Y rows r.
-hipError_t ubqp_launch_ascent(hipStream_t st, const ubqp_problem *p, uint64_t *X, int64_t x_rows, const int32_t *idx,
-                              const int64_t *nidx_d, int64_t offset, int64_t cap, const int32_t *Y, int64_t *f,
-                              int32_t max_flips, int32_t *flips, int32_t *err_flag);
-// Multistart selection kernels (select.hip).
-hipError_t ubqp_launch_seed_init(hipStream_t st, uint64_t *seeds, int64_t S, int32_t n, uint64_t run_seed,
-                                 const uint64_t *deriv_x, ubqp_scal *scal);
-hipError_t ubqp_launch_select(hipStream_t st, int32_t n, int64_t M, int64_t S, int32_t g, uint64_t run_seed,
-                              const uint64_t *X, const int64_t *f, const int32_t *flips, const int32_t *idx,
-                              ubqp_scal *scal, uint64_t *best_x, uint64_t *seeds, int64_t *stats);
+AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, const int32_t *idx, const int64_t *nidx_d,
+                         int64_t offset, int64_t cap, const int32_t *Y, int64_t *f, int32_t max_flips, int32_t *flips,
+                         int32_t *err_flag);
+int ubqp_ascent_nb(const AscArgs &a);
+int64_t ubqp_ascent_waves(const AscArgs &a);
+hipError_t ubqp_launch_ascent(hipStream_t st, const AscArgs &a);
+hipError_t ubqp_launch_ascent_batch(hipStream_t st, int planes, int nb, const AscArgs *args, const int64_t *prefix,
+                                    int count, int64_t waves);
+
+SelArgs ubqp_sel_args(int32_t n, int64_t M, int64_t S, uint64_t run_seed, const uint64_t *X, const int64_t *f,
+                      const int32_t *flips, const int32_t *idx, ubqp_scal *scal, uint64_t *best_x, uint64_t *seeds,
+                      int64_t *stats, const uint64_t *deriv_x, int64_t *f_dump);
+int64_t ubqp_seed_blocks(const SelArgs &a);
+int64_t ubqp_cand_blocks(const SelArgs &a);
+hipError_t ubqp_launch_seed_init(hipStream_t st, const SelArgs &a);
+hipError_t ubqp_launch_seed_init_batch(hipStream_t st, const SelArgs *args, const int64_t *seed_prefix, int count,
+                                       int64_t seed_blocks);
+hipError_t ubqp_launch_dump_batch(hipStream_t st, const SelArgs *args, const int64_t *cand_prefix, int count,
+                                  int64_t cand_blocks);
+// incumbent update + statistics, ranking into seeds 1.., seed 0 and random fill, generation counter
+hipError_t ubqp_launch_select_batch(hipStream_t st, const SelArgs *args, const int64_t *cand_prefix,
+                                    int64_t cand_blocks, const int64_t *seed_prefix, int64_t seed_blocks, int count);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libubqp.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ubqp.h")
 
 UBQP_OK, UBQP_EINVAL, UBQP_ERANGE, UBQP_EASYM, UBQP_ENOMEM, UBQP_EDEVICE = 0, -1, -2, -3, -4, -5
-UBQP_DERIV_START, UBQP_TIMING = 1, 2
+UBQP_DERIV_START, UBQP_TIMING, UBQP_NO_GRAPH = 1, 2, 4
 PHASES = ("diversify", "eval", "screen", "ascent", "select")
 MAX_N, MAX_M, MAX_H = 8192, 1 << 22, 256
 INT64_MIN = -(1 << 63)
@@ -68,6 +68,7 @@ def load():
         "ubqp_destroy": [P],
         "ubqp_sync": [P],
         "ubqp_problem_create": [P, i32, P, ctypes.POINTER(P)],
+        "ubqp_problem_create_typed": [P, i32, P, i32, ctypes.POINTER(P)],
         "ubqp_problem_destroy": [P],
         "ubqp_problem_info": [P, P, P, P],
         "ubqp_diversify": [P, i32, P, i64, i32, P, i64],
@@ -79,6 +80,15 @@ def load():
         "ubqp_run_step": [P, i32],
         "ubqp_run_result": [P, ctypes.POINTER(Result)],
         "ubqp_run_destroy": [P],
+        "ubqp_batch_create": [P, i32, P, ctypes.POINTER(Params), ctypes.POINTER(P)],
+        "ubqp_batch_step": [P, i32],
+        "ubqp_batch_result": [P, i32, ctypes.POINTER(Result)],
+        "ubqp_batch_destroy": [P],
+        "ubqp_server_create": [P, i64, i32, ctypes.POINTER(P)],
+        "ubqp_server_submit": [P, i32, P, i32, ctypes.POINTER(Params), P, P, ctypes.POINTER(i64)],
+        "ubqp_server_wait": [P, i64, P, i32, ctypes.POINTER(i32)],
+        "ubqp_server_stats": [P, P],
+        "ubqp_server_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -86,8 +96,14 @@ def load():
         fn.restype = ctypes.c_int
     L.ubqp_run_footprint.argtypes = [P, ctypes.POINTER(Params)]
     L.ubqp_run_footprint.restype = ctypes.c_int64
+    L.ubqp_batch_footprint.argtypes = [i32, P, ctypes.POINTER(Params)]
+    L.ubqp_batch_footprint.restype = ctypes.c_int64
+    L.ubqp_request_footprint.argtypes = [i32, i32, ctypes.POINTER(Params)]
+    L.ubqp_request_footprint.restype = ctypes.c_int64
     L.ubqp_last_error.argtypes = [P]
     L.ubqp_last_error.restype = ctypes.c_char_p
+    L.ubqp_server_error.argtypes = [P]
+    L.ubqp_server_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -96,18 +112,32 @@ def _words(n: int) -> int:
     return (n + 63) // 64
 
 
+_ELEM = {np.dtype(np.int8): 1, np.dtype(np.int16): 2, np.dtype(np.int32): 4}
+
+
+def _coefficients(Q):
+    """Q as a contiguous int8 / int16 / int32 square array (other integer types become int32)."""
+    Q = np.asarray(Q)
+    if Q.dtype not in _ELEM:
+        Q = Q.astype(np.int32)
+    Q = np.ascontiguousarray(Q)
+    if Q.ndim != 2 or Q.shape[0] != Q.shape[1]:
+        raise ValueError("Q must be square")
+    return Q
+
+
 class Problem:
-    """Q resident on the device (ubqp_problem_create)."""
+    """Q resident on the device (ubqp_problem_create_typed: int8, int16 or int32
+    coefficients, checked and converted on the device)."""
 
     def __init__(self, ctx: "Context", Q):
-        Q = np.ascontiguousarray(Q, dtype=np.int32)
-        if Q.ndim != 2 or Q.shape[0] != Q.shape[1]:
-            raise ValueError("Q must be square")
+        Q = _coefficients(Q)
         self.ctx = ctx
         self.n = int(Q.shape[0])
         self.W = _words(self.n)
         h = ctypes.c_void_p()
-        ctx._call("ubqp_problem_create", ctx.h, self.n, Q.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+        ctx._call("ubqp_problem_create_typed", ctx.h, self.n, Q.ctypes.data_as(ctypes.c_void_p), _ELEM[Q.dtype],
+                  ctypes.byref(h))
         self.h = h
         n_, npad, planes = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         ctx._call("ubqp_problem_info", h, ctypes.byref(n_), ctypes.byref(npad), ctypes.byref(planes))
@@ -170,6 +200,136 @@ class Run:
             pass
 
 
+class Batch:
+    """Several multi-start runs advanced together (ubqp_batch_*): one launch per
+    step covers every instance."""
+
+    def __init__(self, ctx: "Context", probs, params):
+        self.ctx, self.probs = ctx, list(probs)
+        self.params = (Params * len(params))(*params)
+        self.h = None
+        handles = (ctypes.c_void_p * len(self.probs))(*[p.h.value for p in self.probs])
+        self._handles = handles
+        h = ctypes.c_void_p()
+        ctx._call("ubqp_batch_create", ctx.h, len(self.probs), ctypes.cast(handles, ctypes.c_void_p), self.params,
+                  ctypes.byref(h))
+        self.h = h
+
+    def step(self, generations: int = 1):
+        self.ctx._call("ubqp_batch_step", self.h, generations)
+
+    def result(self, i: int) -> dict:
+        out, res = _result_buffers(self.probs[i].W, self.params[i].G)
+        self.ctx._call("ubqp_batch_result", self.h, i, ctypes.byref(res))
+        return _result_dict(out, res)
+
+    def close(self):
+        if self.h is not None:
+            load().ubqp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("generations", ctypes.c_int32),
+                ("best_f", ctypes.c_int64), ("have_best", ctypes.c_int32), ("planes", ctypes.c_int32),
+                ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+SERVER_STATS = ("submitted", "finished", "failed", "generations", "max_running", "pool_high", "waiting", "admitted")
+
+
+def _params(M, H, lam_num, lam_den, G, max_flips=0, run_seed=0, flags=0):
+    return Params(M, H, lam_num, lam_den, G, max_flips, flags, run_seed)
+
+
+def request_footprint(n: int, elem_bytes: int, params: dict) -> int:
+    """Pool bytes a request of n variables occupies while admitted (ubqp_request_footprint)."""
+    pr = _params(**params)
+    return int(load().ubqp_request_footprint(n, elem_bytes, ctypes.byref(pr)))
+
+
+class Server:
+    """The request server (ubqp_server_*): solves submitted problems several at a
+    time on one device, each result equal to the solve run alone.
+
+    Q arrays (int8 / int16 / int32) are kept referenced until their request is
+    reported by wait(); page-locked arrays make the upload asynchronous."""
+
+    def __init__(self, ctx: "Context", pool_bytes: int, max_active: int):
+        self.ctx = ctx
+        self.L = ctx.L
+        self.h = None
+        h = ctypes.c_void_p()
+        ctx._call("ubqp_server_create", ctx.h, int(pool_bytes), int(max_active), ctypes.byref(h))
+        self.h = h
+        self._live = {}
+
+    def _err(self, rc):
+        raise UbqpError(rc, self.L.ubqp_server_error(self.h).decode())
+
+    def submit(self, Q, M, H, lam_num, lam_den, G, max_flips=0, run_seed=0, flags=0) -> int:
+        if isinstance(Q, np.ndarray):
+            Q = _coefficients(Q)
+            n, elem, ptr = int(Q.shape[0]), _ELEM[Q.dtype], Q.ctypes.data
+        else:                                   # a page-locked torch tensor [n, n]
+            if Q.dim() != 2 or Q.shape[0] != Q.shape[1] or not Q.is_contiguous() or Q.device.type != "cpu":
+                raise ValueError("Q must be a contiguous square host tensor")
+            n, elem, ptr = int(Q.shape[0]), Q.element_size(), Q.data_ptr()
+        pr = _params(M, H, lam_num, lam_den, G, max_flips, run_seed, flags)
+        bx = np.zeros(_words(n), np.uint64)
+        st = np.zeros((G, 5), np.int64)
+        rid = ctypes.c_int64()
+        rc = self.L.ubqp_server_submit(self.h, n, ctypes.c_void_p(ptr), elem, ctypes.byref(pr),
+                                       bx.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.byref(rid))
+        if rc != UBQP_OK:
+            self._err(rc)
+        self._live[rid.value] = (Q, bx, st)
+        return rid.value
+
+    def wait(self, timeout_s=None, max_items: int = 256) -> list:
+        """Finished requests (at least one unless the timeout passes), as dicts."""
+        buf = (RequestInfo * max_items)()
+        cnt = ctypes.c_int32()
+        tus = -1 if timeout_s is None else int(timeout_s * 1e6)
+        rc = self.L.ubqp_server_wait(self.h, tus, ctypes.cast(buf, ctypes.c_void_p), max_items, ctypes.byref(cnt))
+        if rc != UBQP_OK:
+            self._err(rc)
+        out = []
+        for k in range(cnt.value):
+            r = buf[k]
+            Q, bx, st = self._live.pop(r.id)
+            out.append(dict(id=r.id, status=r.status, generations=r.generations, best_f=int(r.best_f),
+                            have_best=bool(r.have_best), planes=r.planes, best_x=bx, stats=st[:r.generations],
+                            t_submit_ns=r.t_submit_ns, t_admit_ns=r.t_admit_ns, t_start_ns=r.t_start_ns,
+                            t_done_ns=r.t_done_ns))
+        return out
+
+    def stats(self) -> dict:
+        a = np.zeros(8, np.int64)
+        self.L.ubqp_server_stats(self.h, a.ctypes.data_as(ctypes.c_void_p))
+        return dict(zip(SERVER_STATS, (int(v) for v in a)))
+
+    def close(self):
+        if self.h is not None:
+            self.L.ubqp_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A ubqp_ctx on one device, launching on torch's current stream."""
 
@@ -189,7 +349,7 @@ class Context:
         return self.torch.cuda.current_stream(self.device).cuda_stream
 
     def _call(self, name, *args):
-        if name not in ("ubqp_problem_create", "ubqp_problem_info"):
+        if name not in ("ubqp_problem_info",):
             self.L.ubqp_set_stream(self.h, ctypes.c_void_p(self._stream()))
         rc = getattr(self.L, name)(*args)
         if rc != UBQP_OK:
@@ -256,6 +416,24 @@ class Context:
     def run(self, prob: Problem, M, H, lam_num, lam_den, G, max_flips=0, run_seed=0, flags=0,
             f_dump=None) -> "Run":
         return Run(self, prob, Params(M, H, lam_num, lam_den, G, max_flips, flags, run_seed), f_dump)
+
+    def batch(self, probs, params) -> Batch:
+        """params: list of dicts with keys M, H, lam_num, lam_den, G and optional
+        max_flips, run_seed, flags."""
+        ps = [Params(d["M"], d["H"], d["lam_num"], d["lam_den"], d["G"], d.get("max_flips", 0), d.get("flags", 0),
+                     d.get("run_seed", 0)) for d in params]
+        return Batch(self, probs, ps)
+
+    def multistart_batched(self, probs, params) -> list:
+        b = self.batch(probs, params)
+        try:
+            b.step(params[0]["G"])
+            return [b.result(i) for i in range(len(probs))]
+        finally:
+            b.close()
+
+    def server(self, pool_bytes: int, max_active: int) -> Server:
+        return Server(self, pool_bytes, max_active)
 
     def footprint(self, prob: Problem, M, H, G) -> int:
         pr = Params(M, H, 1, 2, G, 0, 0, 0)

@@ -313,3 +313,53 @@ def test_run_in_steps_equals_one_call(ctx):
     assert (np.diff(r["gen_ms"]) > 0).all() and (r["phase_ms"] >= 0).all()
     with pytest.raises(ubqp.UbqpError):
         ctx.run(prob, **kw).step(6)
+
+
+# --------------------------------------------------------------- batches ----
+
+def _batch_cases():
+    # (n, density, lo, hi, M, H, lam, max_flips): mixed sizes, one- and two-plane instances
+    return [(300, 0.5, -100, 100, 500, 10, (1, 2), 0),
+            (129, 0.3, -32768, 32767, 260, 5, (3, 10), 0),
+            (1100, 0.1, -100, 100, 4500, 10, (1, 2), 0),
+            (64, 0.9, -128, 127, 128, 2, (4, 5), 3),
+            (700, 0.5, -1000, 1000, 1000, 10, (1, 2), 0)]
+
+
+def test_batch_equals_alone_and_oracle(ctx):
+    """Every instance of a batch gives what it gives alone, and (small ones) what
+    the oracle gives."""
+    G = 3
+    probs, params, Qs = [], [], []
+    for k, (n, d, lo, hi, M, H, lam, mf) in enumerate(_batch_cases()):
+        Q = make_instance(n, d, lo, hi, 7000 + k)
+        Qs.append(Q)
+        probs.append(ctx.problem(Q))
+        params.append(dict(M=M, H=H, lam_num=lam[0], lam_den=lam[1], G=G, max_flips=mf, run_seed=40 + k))
+    res = ctx.multistart_batched(probs, params)
+    for k, (prob, pr, r) in enumerate(zip(probs, params, res)):
+        alone = ctx.multistart(prob, **pr)
+        assert np.array_equal(r["stats"], alone["stats"]), k
+        assert r["best_f"] == alone["best_f"] and np.array_equal(r["best_x"], alone["best_x"]), k
+        o = oracle.multistart(Qs[k], threads=8, **pr)
+        assert np.array_equal(r["stats"], o["stats"]) and r["best_f"] == o["best_f"], k
+        assert np.array_equal(r["best_x"], o["best_x"]), k
+
+
+def test_graph_replay_equals_direct_launches(ctx):
+    from paper_1706_00037_amd import ubqp
+    Q = make_instance(900, 0.3, -100, 100, 77)
+    prob = ctx.problem(Q)
+    kw = dict(M=3000, H=10, lam_num=1, lam_den=2, G=4, run_seed=6)
+    a = ctx.multistart(prob, **kw)
+    b = ctx.multistart(prob, flags=ubqp.UBQP_NO_GRAPH, **kw)
+    assert np.array_equal(a["stats"], b["stats"]) and a["best_f"] == b["best_f"]
+    assert np.array_equal(a["best_x"], b["best_x"])
+
+
+def test_batch_rejects_unequal_generation_counts(ctx):
+    from paper_1706_00037_amd import ubqp
+    p1 = ctx.problem(make_instance(50, 0.5, -10, 10, 1))
+    p2 = ctx.problem(make_instance(60, 0.5, -10, 10, 2))
+    with pytest.raises(ubqp.UbqpError):
+        ctx.batch([p1, p2], [dict(M=40, H=2, lam_num=1, lam_den=2, G=2), dict(M=40, H=2, lam_num=1, lam_den=2, G=3)])

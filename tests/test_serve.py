@@ -1,0 +1,178 @@
+"""The request server (serving form) through the C ABI.
+
+Every request's result must equal the result of the same solve run alone
+(ubqp_problem_create_typed + ubqp_multistart), bit for bit, whatever the mix of
+requests it ran beside; small requests are also checked against the oracle.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1706_00037_amd.inputs import make_instance
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ub():
+    from paper_1706_00037_amd import ubqp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ubqp
+
+
+@pytest.fixture(scope="module")
+def ctx(ub):
+    return ub.Context(0)
+
+
+def _requests():
+    # (n, density, lo, hi, dtype, M, H, lam, G, max_flips, flags)
+    return [
+        (300, 0.5, -100, 100, np.int8, 600, 10, (1, 2), 4, 0, 0),
+        (129, 0.3, -32768, 32767, np.int16, 260, 5, (3, 10), 3, 0, 0),
+        (1100, 0.1, -100, 100, np.int8, 2048, 10, (1, 2), 5, 0, 1),
+        (64, 0.9, -128, 127, np.int8, 128, 2, (4, 5), 6, 3, 0),
+        (700, 0.5, -1000, 1000, np.int16, 1000, 10, (1, 2), 2, 0, 0),
+        (1, 1.0, -100, 100, np.int8, 7, 3, (1, 2), 3, 0, 0),
+        (2000, 0.05, -100, 100, np.int8, 1024, 8, (1, 2), 3, 0, 0),
+        (513, 1.0, -100, 100, np.int32, 700, 10, (1, 3), 4, 0, 0),
+        (90, 0.5, -100, 100, np.int8, 100, 5, (1, 1), 2, 0, 0),           # nobody passes
+        (450, 0.2, -30000, 30000, np.int16, 1500, 10, (1, 2), 5, 0, 1),
+    ]
+
+
+def _make(k, case):
+    n, d, lo, hi, dt, M, H, lam, G, mf, fl = case
+    Q = make_instance(n, d, lo, hi, 9100 + k).astype(dt)
+    pr = dict(M=M, H=H, lam_num=lam[0], lam_den=lam[1], G=G, max_flips=mf, flags=fl, run_seed=500 + k)
+    return Q, pr
+
+
+def _alone(ctx, Q, pr):
+    return ctx.multistart(ctx.problem(Q), **pr)
+
+
+def _same(a, b, tag):
+    assert a["have_best"] == b["have_best"], tag
+    assert a["best_f"] == b["best_f"], tag
+    assert np.array_equal(a["stats"], b["stats"]), tag
+    if a["have_best"]:
+        assert np.array_equal(a["best_x"], b["best_x"]), tag
+
+
+def _collect(srv, ids, timeout=120.0):
+    out, t0 = {}, time.monotonic()
+    while len(out) < len(ids):
+        assert time.monotonic() - t0 < timeout, "server did not finish"
+        for r in srv.wait(timeout_s=1.0):
+            out[r["id"]] = r
+    return out
+
+
+def test_typed_problem_equals_int32_problem(ctx):
+    """int8 / int16 host coefficients give the same resident problem as int32 ones."""
+    from paper_1706_00037_amd.inputs import random_candidates
+    for n, lo, hi, dt in [(200, -100, 100, np.int8), (333, -32768, 32767, np.int16), (70, -128, 127, np.int16)]:
+        Q = make_instance(n, 0.4, lo, hi, n)
+        X = random_candidates(300, n, 3)
+        a, b = ctx.problem(Q), ctx.problem(Q.astype(dt))
+        assert a.planes == b.planes
+        fa = torch.zeros(300, dtype=torch.int64, device="cuda")
+        fb = torch.zeros(300, dtype=torch.int64, device="cuda")
+        Xd = torch.from_numpy(X.view(np.int64)).cuda()
+        ctx.eval(a, Xd, fa)
+        ctx.eval(b, Xd, fb)
+        torch.cuda.synchronize()
+        assert torch.equal(fa, fb)
+        assert np.array_equal(fa.cpu().numpy(), oracle.eval_many(Q, X, threads=8))
+
+
+def test_mix_equals_alone_with_forced_interleavings(ctx, ub):
+    """Requests arrive in waves: some while others are uploading, running or
+    finishing.  Each result equals the same solve alone."""
+    cases = [_make(k, c) for k, c in enumerate(_requests())]
+    alone = [_alone(ctx, Q, pr) for Q, pr in cases]
+    srv = ub.Server(ctx, pool_bytes=2 << 30, max_active=4)
+    try:
+        ids = [srv.submit(Q, **pr) for Q, pr in cases[:3]]            # a first wave
+        first = srv.wait(timeout_s=60.0)                               # at least one done
+        assert first
+        got = {r["id"]: r for r in first}
+        ids += [srv.submit(Q, **pr) for Q, pr in cases[3:7]]          # arrive while others run
+        time.sleep(0.002)
+        ids += [srv.submit(Q, **pr) for Q, pr in cases[7:]]
+        got.update(_collect(srv, [i for i in ids if i not in got]))
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["finished"] == len(cases) and st["failed"] == 0
+    assert 1 <= st["max_running"] <= 4
+    for k, i in enumerate(ids):
+        r = got[i]
+        assert r["status"] == ub.UBQP_OK, k
+        assert r["generations"] == cases[k][1]["G"], k
+        _same(r, alone[k], k)
+        assert r["t_submit_ns"] <= r["t_admit_ns"] <= r["t_start_ns"] <= r["t_done_ns"], k
+
+
+def test_mix_matches_oracle(ctx, ub):
+    cases = [_make(k, c) for k, c in enumerate(_requests()) if c[0] <= 700]
+    srv = ub.Server(ctx, pool_bytes=1 << 30, max_active=8)
+    try:
+        ids = [srv.submit(Q, **pr) for Q, pr in cases]
+        got = _collect(srv, ids)
+    finally:
+        srv.close()
+    for (Q, pr), i in zip(cases, ids):
+        o = oracle.multistart(Q.astype(np.int32), threads=8, **pr)
+        _same(got[i], o, i)
+
+
+def test_admission_by_footprint_and_slots(ctx, ub):
+    """A pool that holds two requests at a time: never more than two run, all
+    finish, results unchanged.  max_active = 1 runs them one at a time."""
+    cases = [_make(k, c) for k, c in enumerate(_requests()) if 100 <= c[0] <= 1100]
+    fp = max(ub.request_footprint(Q.shape[0], Q.dtype.itemsize, pr) for Q, pr in cases)
+    alone = [_alone(ctx, Q, pr) for Q, pr in cases]
+    for pool, act, cap in [(2 * fp + 4096, 16, 2), (1 << 30, 1, 1)]:
+        srv = ub.Server(ctx, pool_bytes=pool, max_active=act)
+        try:
+            ids = [srv.submit(Q, **pr) for Q, pr in cases]
+            got = _collect(srv, ids)
+            st = srv.stats()
+        finally:
+            srv.close()
+        assert st["max_running"] <= cap and st["pool_high"] <= pool
+        for k, i in enumerate(ids):
+            _same(got[i], alone[k], (pool, act, k))
+
+
+def test_request_errors(ctx, ub):
+    srv = ub.Server(ctx, pool_bytes=64 << 20, max_active=2)
+    try:
+        Q = make_instance(100, 0.5, -100, 100, 5).astype(np.int8)
+        bad = Q.copy()
+        bad[3, 7] = bad[7, 3] + 1                                      # asymmetric
+        wide = make_instance(100, 0.5, -100, 100, 6).astype(np.int32)
+        wide[4, 4] = 40000                                             # out of range
+        pr = dict(M=100, H=5, lam_num=1, lam_den=2, G=2, run_seed=1)
+        i_bad = srv.submit(bad, **pr)
+        i_ok = srv.submit(Q, **pr)
+        i_wide = srv.submit(wide, **pr)
+        got = _collect(srv, [i_bad, i_ok, i_wide])
+        with pytest.raises(ub.UbqpError):                              # larger than the pool
+            srv.submit(np.zeros((8000, 8000), np.int8), **pr)
+        with pytest.raises(ub.UbqpError):                              # flags beyond DERIV_START
+            srv.submit(Q, **dict(pr, flags=ub.UBQP_TIMING))
+        with pytest.raises(ub.UbqpError):                              # G < 1
+            srv.submit(Q, **dict(pr, G=0))
+    finally:
+        srv.close()
+    assert got[i_bad]["status"] == ub.UBQP_EASYM
+    assert got[i_wide]["status"] == ub.UBQP_ERANGE
+    assert got[i_ok]["status"] == ub.UBQP_OK
+    _same(got[i_ok], _alone(ctx, Q, pr), "ok")
