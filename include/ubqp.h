@@ -53,6 +53,10 @@ extern "C" {
 #define UBQP_DERIV_START 1u /* generation-0 seed 0 is the first-derivative solution */
 #define UBQP_TIMING 2u      /* record stream events around every phase of a generation */
 #define UBQP_NO_GRAPH 4u    /* launch every kernel directly instead of replaying a captured generation */
+#define UBQP_AUTOTUNE 8u    /* tune the evaluation's tiling for every instance first (ubqp_tune_eval) */
+
+/* variants of the evaluation's matrix-core tiling (ubqp_tune_eval) */
+#define UBQP_EVAL_VARIANTS 6
 
 /* phases of a generation, in order (ubqp_result.phase_ms_host) */
 #define UBQP_PHASE_DIVERSIFY 0
@@ -75,7 +79,7 @@ typedef struct {
     int32_t lam_den;
     int32_t G;          /* generations (iterations of the main loop), >= 1             */
     int32_t max_flips;  /* flips per ascent, 0 = until a 1-flip local optimum          */
-    uint32_t flags;     /* UBQP_DERIV_START | UBQP_TIMING | UBQP_NO_GRAPH              */
+    uint32_t flags;     /* UBQP_DERIV_START | UBQP_TIMING | UBQP_NO_GRAPH | UBQP_AUTOTUNE */
     uint64_t run_seed;  /* SplitMix64 seed of the random solutions                     */
 } ubqp_params;
 
@@ -146,6 +150,24 @@ UBQP_API int ubqp_diversify(ubqp_ctx *ctx, int32_t n, const uint64_t *seeds_d, i
  */
 UBQP_API int ubqp_eval(ubqp_ctx *ctx, const ubqp_problem *prob, const uint64_t *X_d, int64_t M,
               int64_t *f_d);
+
+/*
+ * Autotuning of the evaluation (the contraction behind ubqp_eval and every
+ * multi-start generation).  Variant v stages K 64, 128 or 256 deep (v / 2 = 0, 1,
+ * 2) and orders workgroup tiles n-tile-major (v even) or m-tile-major (v odd);
+ * all variants give identical results.  ubqp_tune_eval times each variant on
+ * prob with M synthetic candidates (M rounded up to a power of two, at least
+ * 256), remembers the fastest for (planes, n_pad, that M) for the life of the
+ * process, and returns it in *variant (may be NULL) with the milliseconds of
+ * every variant in ms_host[UBQP_EVAL_VARIANTS] (may be NULL).  Cached keys
+ * return at once.  Later ubqp_eval calls, runs, batches and server generations
+ * use the chosen variant.  Synchronous.
+ * ubqp_eval_variant is ubqp_eval with an explicit variant.
+ */
+UBQP_API int ubqp_tune_eval(ubqp_ctx *ctx, const ubqp_problem *prob, int64_t M, int32_t *variant, double *ms_host);
+UBQP_API int ubqp_eval_variant(ubqp_ctx *ctx, const ubqp_problem *prob, const uint64_t *X_d, int64_t M,
+                               int64_t *f_d, int32_t variant);
+
 
 /*
  * Screening (Pseudocode section): T(lambda) = Mean + lambda (Max - Mean) over

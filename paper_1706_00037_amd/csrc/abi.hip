@@ -173,7 +173,7 @@ int ubqp_eval(ubqp_ctx *ctx, const ubqp_problem *p, const uint64_t *X_d, int64_t
     if (!ctx || !p || !X_d || !f_d) return ubqp_fail(ctx, UBQP_EINVAL, "null argument");
     UBQP_TRY(check_words(ctx, p->n, M));
     UBQP_TRY(ubqp_set_device(ctx));
-    UBQP_HIP_TRY(ctx, ubqp_launch_eval(ctx->stream, ubqp_eval_args(p, X_d, M, f_d)));
+    UBQP_HIP_TRY(ctx, ubqp_launch_eval_v(ctx->stream, ubqp_eval_args(p, X_d, M, f_d), ubqp_eval_variant_for(p, M)));
     return UBQP_OK;
 }
 

@@ -32,201 +32,6 @@
 namespace {
 
 
-template <typename QT> struct RowLoad;
-template <> struct RowLoad<int8_t> {
-    // 16 consecutive int8 entries
-    __device__ static inline void load(const int8_t *p, int32_t (&q)[16])
-    {
-        const uint4 v = *(const uint4 *)p;
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-            for (int k = 0; k < 4; k++) q[i * 4 + k] = ((int32_t)(w[i] << (24 - 8 * k))) >> 24;
-    }
-};
-template <> struct RowLoad<int16_t> {
-    __device__ static inline void load(const int16_t *p, int32_t (&q)[16])
-    {
-        const uint4 v0 = *(const uint4 *)p, v1 = *(const uint4 *)(p + 8);
-        const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            q[i * 2] = ((int32_t)(w[i] << 16)) >> 16;
-            q[i * 2 + 1] = ((int32_t)w[i]) >> 16;
-        }
-    }
-};
-
-// Lane-local column index of register slot (b, t): local = 16 b + t (< 128);
-// global column = 1024 b + 16 lane + t.
-__device__ inline int32_t global_col(int32_t local, int lane) { return (local >> 4) * 1024 + lane * 16 + (local & 15); }
-
-// Wave-wide max of (value, column) pairs: largest value, lowest column.
-__device__ inline void wave_argmax(int32_t &v, int32_t &k)
-{
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t ov = __shfl_xor(v, o), ok = __shfl_xor(k, o);
-        if (ov > v || (ov == v && ok < k)) { v = ov; k = ok; }
-    }
-}
-
-template <int NB, typename QT>
-__device__ void ascend_one(const AscArgs &a, int64_t p, int lane)
-{
-    // int8 Q: |g| < 2^21 for n <= 8192, so the argmax runs on packed 32-bit keys
-    //   key = Delta * 128 + L,  L = 127 - local   (largest key: largest Delta,
-    //                                              then lowest local index).
-    // The register holds h = g * 128 + L, i.e. the key while x = 0; for x = 1 the
-    // key is -g * 128 + L = -h + 2L = (h ^ m) + (m & (2L + 1)) with m = -x, one
-    // v_xad.  The flip update adds 256 d q_ik to h and leaves L alone.
-    // int16 Q keeps g and compares (Delta, column) pairs directly.
-    constexpr bool KEYED = false;  // the int8 path is ascend_i8
-    const int64_t c = a.idx[a.offset + p];
-    if (c < 0 || c >= a.x_rows) {
-        if (lane == 0) atomicOr(a.err, 2);
-        return;
-    }
-    uint64_t *xr = a.X + c * a.W;
-    const QT *qa = (const QT *)a.qa;
-
-    uint32_t xb[NB];
-    int32_t gv[NB][16];
-    int pc = 0;
-#pragma unroll
-    for (int b = 0; b < NB; b++) {
-        const int col0 = b * 1024 + lane * 16;
-        uint32_t bits = 0;
-        if (col0 < a.n_pad) {
-            const int w = col0 >> 6;
-            if (w < a.W) bits = (uint32_t)(xr[w] >> (col0 & 63)) & 0xFFFFu;
-        }
-        xb[b] = bits;
-        pc += __popc(bits);
-    }
-    if (a.planes == 2) {
-        for (int o = 32; o > 0; o >>= 1) pc += __shfl_xor(pc, o);
-    }
-    const int64_t ystride = a.max_idx * a.n_pad;
-#pragma unroll
-    for (int b = 0; b < NB; b++) {
-        const int col0 = b * 1024 + lane * 16;
-        if (col0 < a.n_pad) {
-            const int32_t *y0 = a.Y + p * a.n_pad + col0;
-#pragma unroll
-            for (int t4 = 0; t4 < 4; t4++) {
-                const int4 v = *(const int4 *)(y0 + t4 * 4);
-                const int4 dg = *(const int4 *)(a.diag + col0 + t4 * 4);
-                int32_t y[4] = {v.x, v.y, v.z, v.w};
-                const int32_t d[4] = {dg.x, dg.y, dg.z, dg.w};
-                if (a.planes == 2) {
-                    const int4 u = *(const int4 *)(y0 + ystride + t4 * 4);
-                    const int32_t y1[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-                    for (int k = 0; k < 4; k++) y[k] = (int32_t)a.weight0 * y[k] + y1[k] + (int32_t)a.bias * pc;
-                }
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const int t = t4 * 4 + k;
-                    // padding columns (j >= n) keep g = 0, so their Delta is 0 and never taken
-                    const int32_t g = col0 + t < a.n ? 2 * y[k] + (((xb[b] >> t) & 1u) ? -d[k] : d[k]) : 0;
-                    gv[b][t] = KEYED ? g * 128 + (127 - (b * 16 + t)) : g;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < 16; t++) gv[b][t] = KEYED ? (127 - (b * 16 + t)) : 0;
-        }
-    }
-
-    // (V, K): largest Delta and its lowest global column, identical in all lanes.
-    auto argmax = [&](int32_t &V, int32_t &K) {
-        if constexpr (KEYED) {
-            int32_t best = INT32_MIN;
-#pragma unroll
-            for (int b = 0; b < NB; b++)
-#pragma unroll
-                for (int t = 0; t < 16; t += 2) {
-                    const int32_t m0 = -(int32_t)((xb[b] >> t) & 1u), m1 = -(int32_t)((xb[b] >> (t + 1)) & 1u);
-                    const int32_t k0 = (gv[b][t] ^ m0) + (m0 & (2 * (127 - (b * 16 + t)) + 1));
-                    const int32_t k1 = (gv[b][t + 1] ^ m1) + (m1 & (2 * (127 - (b * 16 + t + 1)) + 1));
-                    best = max(best, max(k0, k1));
-                }
-            int32_t v = best >> 7;
-            int32_t k = global_col(127 - (best & 127), lane);
-            wave_argmax(v, k);
-            V = v;
-            K = k;
-        } else {
-            int32_t bv = INT32_MIN, bk = 0x7FFFFFFF;
-#pragma unroll
-            for (int b = 0; b < NB; b++)
-#pragma unroll
-                for (int t = 0; t < 16; t++) {
-                    const int32_t m = -(int32_t)((xb[b] >> t) & 1u);
-                    const int32_t dl = (gv[b][t] ^ m) - m;
-                    if (dl > bv) { bv = dl; bk = b * 16 + t; }
-                }
-            bk = global_col(bk, lane);
-            wave_argmax(bv, bk);
-            V = bv;
-            K = bk;
-        }
-    };
-
-    int64_t fv = a.f[c];
-    int32_t flips = 0;
-    const int32_t cap = a.max_flips > 0 ? a.max_flips : a.safety_cap;
-    int32_t V, K;
-    argmax(V, K);
-    while (V > 0 && flips < cap) {
-        const int kb = K >> 10, kl = (K >> 4) & 63, kt = K & 15;
-        uint32_t xw = 0;
-#pragma unroll
-        for (int b = 0; b < NB; b++) xw = (b == kb) ? xb[b] : xw;
-        const int xk = (__shfl((int)xw, kl) >> kt) & 1;
-        if (lane == kl) {
-#pragma unroll
-            for (int b = 0; b < NB; b++) xb[b] ^= (b == kb) ? (1u << kt) : 0u;
-        }
-        // g_i += 2 d q_ik with d = +1 (x_k: 0 -> 1) or -1; scaled by 128 when keyed
-        const int32_t step = (xk ? -2 : 2) * (KEYED ? 128 : 1);
-        fv += V;
-        flips++;
-        const QT *row = qa + (int64_t)K * a.n_pad;
-#pragma unroll
-        for (int b = 0; b < NB; b++) {
-            const int col0 = b * 1024 + lane * 16;
-            if (col0 < a.n_pad) {
-                int32_t q[16];
-                RowLoad<QT>::load(row + col0, q);
-#pragma unroll
-                for (int t = 0; t < 16; t++) gv[b][t] += step * q[t];
-            }
-        }
-        argmax(V, K);
-    }
-    if (V > 0 && a.max_flips == 0 && lane == 0) atomicOr(a.err, 1);  // safety cap reached
-
-#pragma unroll
-    for (int b = 0; b < NB; b++) {
-        const int col0 = b * 1024 + lane * 16;
-        const uint64_t v0 = xb[b];
-        const uint64_t v1 = (uint32_t)__shfl_down((int)xb[b], 1);
-        const uint64_t v2 = (uint32_t)__shfl_down((int)xb[b], 2);
-        const uint64_t v3 = (uint32_t)__shfl_down((int)xb[b], 3);
-        if ((lane & 3) == 0 && col0 < a.n_pad) {
-            const int w = col0 >> 6;
-            if (w < a.W) xr[w] = v0 | (v1 << 16) | (v2 << 32) | (v3 << 48);
-        }
-    }
-    if (lane == 0) {
-        a.f[c] = fv;
-        a.flips[c] = flips;
-    }
-}
-
 // key += (q * s) * step, q = signed byte B of w, s = signed byte B of u, step
 // wave-uniform: one SDWA multiply (both bytes sign-extended) and one 24-bit mad.
 template <int B>
@@ -254,19 +59,24 @@ __device__ inline int32_t wave_max_i32(int32_t v)
 
 typedef int32_t v16i __attribute__((ext_vector_type(16)));
 
+// Column ownership of the int8 ascent: lane l owns [l PL, (l+1) PL), PL = 16 NB.
+// (Measured against lane l owning 1024 b + 16 l + t, which makes each 16-byte
+// row load of a wave one contiguous KB but needs a DPP min for the tie-break: the
+// contiguous ranges were 3% faster.)
+template <int NB> __device__ inline int asc_col0(int lane, int b) { return lane * 16 * NB + 16 * b; }
+
 template <int NB>
 __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
 {
-    constexpr int PL = 16 * NB;
     const int64_t c = a.idx[a.offset + p];
     if (c < 0 || c >= a.x_rows) {
         if (lane == 0) atomicOr(a.err, 2);
         return;
     }
     uint64_t *xr = a.X + c * a.W;
-    const int col_base = lane * PL;
-    // key_i = Delta_i * 256 + 2 L_i + x_i,  L_i = 127 - local_i: the largest key is
-    // the largest Delta, then the lowest local index; bit 0 carries x_i.
+    // key_i = Delta_i * 256 + 2 L_i + x_i,  L_i = 127 - local_i (local = 16 b + t):
+    // the largest key is the largest Delta, then the lowest local index (the
+    // lowest column of the lane); bit 0 carries x_i.
     v16i kk[NB];
     // s_i = 1 - 2 x_i as signed bytes, four per register
     uint32_t ss[NB][4];
@@ -274,7 +84,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
     // (Delta = 0, x = 0) are synthesised
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const int col0 = col_base + 16 * b;
+        const int col0 = asc_col0<NB>(lane, b);
         const bool in = col0 < a.n_pad;
         const int32_t *yrow = a.Y + p * a.n_pad + col0;
 #pragma unroll
@@ -308,12 +118,12 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         const int32_t ld = best >> 8;
         V = wave_max_i32(ld);
         if (V <= 0 || flips >= cap) break;
-        const uint64_t bal = __ballot(ld == V);
-        const int lstar = __ffsll((unsigned long long)bal) - 1;
+        // the lowest lane attaining V holds the lowest column (lanes own ordered ranges)
+        const int lstar = __ffsll((unsigned long long)__ballot(ld == V)) - 1;
         const int32_t bk = __builtin_amdgcn_readlane(best, lstar);
         const int local = 127 - ((bk >> 1) & 127);
         const int32_t xk = bk & 1;              // x_k before the flip
-        const int K = lstar * PL + local;
+        const int K = asc_col0<NB>(lstar, local >> 4) + (local & 15);
         const int bs = local >> 4, ts = local & 15;
         // the flipped variable: Delta_k -> -V, x_k and s_k toggle (lane lstar only)
         const bool own = lane == lstar;
@@ -332,20 +142,21 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         flips++;
         // Delta_i += 2 d s_i q_ik for i != k, with d = 1 - 2 x_k: key_i += (q_ik s_i) * 512 d
         const int32_t step = xk ? -512 : 512;
-        const int8_t *row = qa + (int64_t)K * a.ncol_a + col_base;
+        const int8_t *row = qa + (int64_t)K * a.ncol_a;
         uint4 w[NB];
 #pragma unroll
-        for (int b = 0; b < NB; b++) w[b] = *(const uint4 *)(row + 16 * b);
+        for (int b = 0; b < NB; b++) w[b] = *(const uint4 *)(row + asc_col0<NB>(lane, b));
 #pragma unroll
         for (int b = 0; b < NB; b++) {
             const uint32_t q4[4] = {w[b].x, w[b].y, w[b].z, w[b].w};
+            const uint32_t s4[4] = {ss[b][0], ss[b][1], ss[b][2], ss[b][3]};
 #pragma unroll
             for (int t = 0; t < 16; t++) {
                 switch (t & 3) {
-                case 0: kk[b][t] = update_key<0>(kk[b][t], q4[t >> 2], ss[b][t >> 2], step); break;
-                case 1: kk[b][t] = update_key<1>(kk[b][t], q4[t >> 2], ss[b][t >> 2], step); break;
-                case 2: kk[b][t] = update_key<2>(kk[b][t], q4[t >> 2], ss[b][t >> 2], step); break;
-                default: kk[b][t] = update_key<3>(kk[b][t], q4[t >> 2], ss[b][t >> 2], step); break;
+                case 0: kk[b][t] = update_key<0>(kk[b][t], q4[t >> 2], s4[t >> 2], step); break;
+                case 1: kk[b][t] = update_key<1>(kk[b][t], q4[t >> 2], s4[t >> 2], step); break;
+                case 2: kk[b][t] = update_key<2>(kk[b][t], q4[t >> 2], s4[t >> 2], step); break;
+                default: kk[b][t] = update_key<3>(kk[b][t], q4[t >> 2], s4[t >> 2], step); break;
                 }
             }
         }
@@ -357,6 +168,181 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         uint32_t bits = 0;
 #pragma unroll
         for (int t = 0; t < 16; t++) bits |= ((uint32_t)kk[b][t] & 1u) << t;
+        const int ci = asc_col0<NB>(lane, b) >> 4;
+        if (ci < 4 * a.W) ((uint16_t *)xr)[ci] = (uint16_t)bits;
+    }
+    if (lane == 0) {
+        a.f[c] = fv;
+        a.flips[c] = flips;
+    }
+}
+
+// delta += (q * s) * step, q = signed word W of w, s = signed byte B of u.
+template <int Wd, int B>
+__device__ inline int32_t update_delta16(int32_t delta, uint32_t w, uint32_t u, int32_t step)
+{
+    int32_t prod;
+    asm("v_mul_i32_i24_sdwa %1, sext(%2), sext(%3) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_%5 "
+        "src1_sel:BYTE_%6\n\t"
+        "v_mad_i32_i24 %0, %1, %4, %0"
+        : "+v"(delta), "=&v"(prod)
+        : "v"(w), "v"(u), "s"(step), "n"(Wd), "n"(B));
+    return delta;
+}
+
+// Largest of 16 values.
+__device__ inline int32_t max16(const v16i &v)
+{
+    const int32_t a = max(max(v[0], v[1]), v[2]), b = max(max(v[3], v[4]), v[5]), c = max(max(v[6], v[7]), v[8]);
+    const int32_t d = max(max(v[9], v[10]), v[11]), e = max(max(v[12], v[13]), v[14]);
+    return max(max(max(a, b), max(c, d)), max(e, v[15]));
+}
+
+// int16 Q: |Delta| < 2^30, too wide to share 32 bits with a column index, so the
+// lane keeps Delta_i itself (and s_i as a byte) for its contiguous columns
+// [l PL, (l+1) PL).  Per flip: the maximum of each 16-column block, the lane's
+// and the wave's maximum V; the lowest lane attaining V, then (in that lane) its
+// lowest block and lowest column attaining V -- the lowest global column.  The
+// update is one SDWA multiply (q word x s byte) and one mad by the uniform 2 d.
+template <int NB>
+__device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
+{
+    constexpr int PL = 16 * NB;
+    const int64_t c = a.idx[a.offset + p];
+    if (c < 0 || c >= a.x_rows) {
+        if (lane == 0) atomicOr(a.err, 2);
+        return;
+    }
+    uint64_t *xr = a.X + c * a.W;
+    const int col_base = lane * PL;
+    // popcount(x) for the constant part of the split planes
+    int pc = 0;
+    for (int w = lane; w < a.W; w += 64) pc += __popcll(xr[w]);
+    for (int o = 32; o > 0; o >>= 1) pc += __shfl_xor(pc, o);
+    v16i dl[NB];
+    uint32_t ss[NB][4];
+    const int64_t ystride = a.max_idx * a.n_pad;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int col0 = col_base + 16 * b;
+        const bool in = col0 < a.n_pad;
+        uint32_t bits = 0;
+        if (in) {
+            const int w = col0 >> 6;
+            if (w < a.W) bits = (uint32_t)(xr[w] >> (col0 & 63)) & 0xFFFFu;
+        }
+#pragma unroll
+        for (int t4 = 0; t4 < 4; t4++) {
+            int4 v0 = {0, 0, 0, 0}, v1 = {0, 0, 0, 0}, dg = {0, 0, 0, 0};
+            if (in) {
+                v0 = *(const int4 *)(a.Y + p * a.n_pad + col0 + 4 * t4);
+                v1 = *(const int4 *)(a.Y + ystride + p * a.n_pad + col0 + 4 * t4);
+                dg = *(const int4 *)(a.diag + col0 + 4 * t4);
+            }
+            const int32_t y0[4] = {v0.x, v0.y, v0.z, v0.w}, y1[4] = {v1.x, v1.y, v1.z, v1.w};
+            const int32_t d[4] = {dg.x, dg.y, dg.z, dg.w};
+            uint32_t sw = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int t = 4 * t4 + k;
+                const bool xi = (bits >> t) & 1u;
+                // y = (x Q)_j = 256 Y_hi + Y_lo + 128 popcount(x); g = 2 y + q_jj (1 - 2 x_j)
+                const int32_t y = (int32_t)a.weight0 * y0[k] + y1[k] + (int32_t)a.bias * pc;
+                const int32_t g = 2 * y + (xi ? -d[k] : d[k]);
+                // padding columns (j >= n) keep Delta = 0, so they are never taken
+                dl[b][t] = (in && col0 + t < a.n) ? (xi ? -g : g) : 0;
+                sw |= (xi ? 0xFFu : 0x01u) << (8 * k);
+            }
+            ss[b][t4] = sw;
+        }
+    }
+
+    const int16_t *qa = (const int16_t *)a.qa;
+    int64_t fv = a.f[c];
+    int32_t flips = 0;
+    const int32_t cap = a.max_flips > 0 ? a.max_flips : a.safety_cap;
+    int32_t V;
+    for (;;) {
+        int32_t bm[NB];
+#pragma unroll
+        for (int b = 0; b < NB; b++) bm[b] = max16(dl[b]);
+        int32_t best = bm[0];
+#pragma unroll
+        for (int b = 1; b < NB; b++) best = max(best, bm[b]);
+        V = wave_max_i32(best);
+        if (V <= 0 || flips >= cap) break;
+        const int lstar = __ffsll((unsigned long long)__ballot(best == V)) - 1;
+        int bsel = NB - 1;
+#pragma unroll
+        for (int b = NB - 2; b >= 0; b--) bsel = bm[b] == V ? b : bsel;
+        const int bs = __builtin_amdgcn_readlane(bsel, lstar);
+        int tsel = 15;
+        uint32_t sword = 0;
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            if (b == bs) {
+#pragma unroll
+                for (int t = 14; t >= 0; t--) tsel = dl[b][t] == V ? t : tsel;
+            }
+        }
+        const int ts = __builtin_amdgcn_readlane(tsel, lstar);
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                if (b == bs && r == (ts >> 2)) sword = ss[b][r];
+        const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)sword, lstar);
+        const int32_t xk = ((sk >> (8 * (ts & 3))) & 0xFFu) == 0xFFu;   // x_k before the flip
+        const int K = lstar * PL + 16 * bs + ts;
+        const bool own = lane == lstar;
+        const uint32_t sflip = own ? 0xFEu << (8 * (ts & 3)) : 0u;
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            if (b == bs) {
+                const int32_t ko = dl[b][ts];
+                dl[b][ts] = own ? -V : ko;
+#pragma unroll
+                for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts >> 2)) ? sflip : 0u;
+            }
+        }
+        fv += V;
+        flips++;
+        // Delta_i += 2 d s_i q_ik for i != k, d = 1 - 2 x_k (the ascent matrix has q_kk = 0)
+        const int32_t step = xk ? -2 : 2;
+        const int16_t *row = qa + (int64_t)K * a.ncol_a + col_base;
+        uint4 w[NB][2];
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            w[b][0] = *(const uint4 *)(row + 16 * b);
+            w[b][1] = *(const uint4 *)(row + 16 * b + 8);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            const uint32_t q8[8] = {w[b][0].x, w[b][0].y, w[b][0].z, w[b][0].w,
+                                    w[b][1].x, w[b][1].y, w[b][1].z, w[b][1].w};
+#pragma unroll
+            for (int t = 0; t < 16; t++) {
+                const uint32_t qw = q8[t >> 1], sw = ss[b][t >> 2];
+                switch (t & 7) {
+                case 0: dl[b][t] = update_delta16<0, 0>(dl[b][t], qw, sw, step); break;
+                case 1: dl[b][t] = update_delta16<1, 1>(dl[b][t], qw, sw, step); break;
+                case 2: dl[b][t] = update_delta16<0, 2>(dl[b][t], qw, sw, step); break;
+                case 3: dl[b][t] = update_delta16<1, 3>(dl[b][t], qw, sw, step); break;
+                case 4: dl[b][t] = update_delta16<0, 0>(dl[b][t], qw, sw, step); break;
+                case 5: dl[b][t] = update_delta16<1, 1>(dl[b][t], qw, sw, step); break;
+                case 6: dl[b][t] = update_delta16<0, 2>(dl[b][t], qw, sw, step); break;
+                default: dl[b][t] = update_delta16<1, 3>(dl[b][t], qw, sw, step); break;
+                }
+            }
+        }
+    }
+    if (V > 0 && a.max_flips == 0 && lane == 0) atomicOr(a.err, 1);  // safety cap reached
+
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        uint32_t bits = 0;
+#pragma unroll
+        for (int t = 0; t < 16; t++) bits |= (((ss[b][t >> 2] >> (8 * (t & 3))) & 0xFFu) == 0xFFu ? 1u : 0u) << t;
         const int ci = lane * NB + b;
         if (ci < 4 * a.W) ((uint16_t *)xr)[ci] = (uint16_t)bits;
     }
@@ -368,8 +354,16 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
 
 // One wave per workgroup: a wave whose candidate needs few flips retires at once
 // and its slot is refilled, instead of idling until the slowest wave of a group.
+// Registers hold the keys and signs of 16 NB columns per lane: NB <= 4 fits four
+// waves per SIMD, NB <= 6 three, NB = 7, 8 two.  (Keeping the signs in LDS to fit
+// a third wave at NB = 7 was measured slower: the row delivery, not latency, is the
+// limit.)
+template <int NB> struct AscOcc {
+    static constexpr int waves = NB <= 4 ? 4 : NB <= 6 ? 3 : 2;
+};
+
 template <int NB>
-__global__ __launch_bounds__(64) void ascent_i8_kernel(AscArgs a)
+__global__ __launch_bounds__(64, AscOcc<NB>::waves) void ascent_i8_kernel(AscArgs a)
 {
     const int lane = threadIdx.x;
     int64_t P = *a.nidx_d - a.offset;
@@ -377,27 +371,27 @@ __global__ __launch_bounds__(64) void ascent_i8_kernel(AscArgs a)
     for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_i8<NB>(a, p, lane);
 }
 
-template <int NB, typename QT>
-__global__ __launch_bounds__(64) void ascent_kernel(AscArgs a)
+template <int NB>
+__global__ __launch_bounds__(64, NB <= 4 ? 3 : 2) void ascent_i16_kernel(AscArgs a)
 {
     int64_t P = *a.nidx_d - a.offset;
     P = P < a.max_idx ? P : a.max_idx;
-    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_one<NB, QT>(a, p, threadIdx.x);
+    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_i16<NB>(a, p, threadIdx.x);
 }
 
-template <int NB, typename QT>
-__global__ __launch_bounds__(64) void ascent_batched(const AscArgs *args, const int64_t *prefix, int count)
+template <int NB>
+__global__ __launch_bounds__(64, NB <= 4 ? 3 : 2) void ascent_i16_batched(const AscArgs *args, const int64_t *prefix, int count)
 {
     const int i = ubqp_find_inst(prefix, count, blockIdx.x);
     const AscArgs a = args[i];
     const int64_t w0 = blockIdx.x - prefix[i], nw = prefix[i + 1] - prefix[i];
     int64_t P = *a.nidx_d - a.offset;
     P = P < a.max_idx ? P : a.max_idx;
-    for (int64_t p = w0; p < P; p += nw) ascend_one<NB, QT>(a, p, threadIdx.x);
+    for (int64_t p = w0; p < P; p += nw) ascend_i16<NB>(a, p, threadIdx.x);
 }
 
 template <int NB>
-__global__ __launch_bounds__(64) void ascent_i8_batched(const AscArgs *args, const int64_t *prefix, int count)
+__global__ __launch_bounds__(64, AscOcc<NB>::waves) void ascent_i8_batched(const AscArgs *args, const int64_t *prefix, int count)
 {
     const int i = ubqp_find_inst(prefix, count, blockIdx.x);
     const AscArgs a = args[i];
@@ -456,7 +450,7 @@ int64_t ubqp_ascent_waves(const AscArgs &a) { return a.max_idx < 8192 ? (a.max_i
 hipError_t ubqp_launch_ascent(hipStream_t st, const AscArgs &a)
 {
     const unsigned waves = (unsigned)ubqp_ascent_waves(a);
-#define L16(NB) hipLaunchKernelGGL((ascent_kernel<NB, int16_t>), dim3(waves), dim3(64), 0, st, a)
+#define L16(NB) hipLaunchKernelGGL(ascent_i16_kernel<NB>, dim3(waves), dim3(64), 0, st, a)
 #define L8(NB) hipLaunchKernelGGL(ascent_i8_kernel<NB>, dim3(waves), dim3(64), 0, st, a)
     if (a.planes == 2) {
         UBQP_NB_SWITCH(ubqp_ascent_nb(a), L16)
@@ -472,7 +466,7 @@ hipError_t ubqp_launch_ascent_batch(hipStream_t st, int planes, int nb, const As
                                     int count, int64_t waves)
 {
     if (waves <= 0) return hipSuccess;
-#define L16(NB) hipLaunchKernelGGL((ascent_batched<NB, int16_t>), dim3((unsigned)waves), dim3(64), 0, st, args, prefix, count)
+#define L16(NB) hipLaunchKernelGGL(ascent_i16_batched<NB>, dim3((unsigned)waves), dim3(64), 0, st, args, prefix, count)
 #define L8(NB) hipLaunchKernelGGL(ascent_i8_batched<NB>, dim3((unsigned)waves), dim3(64), 0, st, args, prefix, count)
     if (planes == 2) {
         UBQP_NB_SWITCH(nb, L16)

@@ -9,8 +9,14 @@
 // column j of Q is row j: both operands are K-contiguous and the B fragment of
 // a lane is 16 consecutive bytes of one Q row.
 //
-// Exactness: |Y_mj| <= 128 n <= 2^20 for n <= 8192, inside int32; the row dot
-// is summed per 64-column slab in int32 (<= 2^26) and accumulated across slabs
+// The objective uses only the lower triangle of Q (Q is symmetric):
+//     f_m = sum_j x_mj (2 acc_mj - q_jj),  acc_mj = sum_{i <= j} x_mi q_ij,
+// so a tile of columns [n0, n0 + 128) contracts K over [0, n0 + 128) only, half
+// the dense work overall (the Delta initialisation needs the full Y and keeps
+// the full K range).
+//
+// Exactness: |acc_mj| <= 128 n <= 2^20 for n <= 8192, inside int32; the row dot
+// is summed per 128-column tile in int32 (< 2^31) and accumulated across tiles
 // and planes with int64 atomics (integer, so the order does not matter).
 //
 // Workgroup tile BM x BN = 256 x 128: four waves of 64 rows x 128 columns
@@ -79,6 +85,11 @@ template <int EPI, int KC>
 __device__ void eval_body(const EvalArgs &a, int64_t tile)
 {
     constexpr bool STORE_Y = EPI != EPI_ROWDOT;
+    // The objective needs only the lower triangle of the symmetric Q:
+    //     f = sum_j x_j (2 acc_j - q_jj),   acc_j = sum_{i <= j} q_ij x_i,
+    // so the row-dot tile of columns [n0, n0 + BN) contracts K over [0, n0 + BN)
+    // with the entries k > j of its diagonal block zeroed when they are staged.
+    constexpr bool TRI = EPI == EPI_ROWDOT;
     constexpr int BPITCH = KC + 16;       // bytes per staged Q row (16-byte skew: conflict-free reads)
     constexpr int APITCH = KC / 64 + 1;   // words per staged X row (odd: conflict-free 8-byte reads)
     constexpr int NSUB = KC / 32;         // 32-deep MFMA substeps per K step
@@ -91,7 +102,16 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     const int64_t T = (int64_t)a.m_tiles * a.n_tiles;
     const int plane = (int)(tile / T);
     const int64_t t = tile - plane * T;
-    const int nt = (int)(t / a.m_tiles), mt = (int)(t % a.m_tiles);
+    // tile order: n-tile-major (workgroups adjacent in t share a Q column block)
+    // or m-tile-major (they share an X row block)
+    int nt = a.order ? (int)(t % a.n_tiles) : (int)(t / a.m_tiles);
+    const int mt = a.order ? (int)(t / a.n_tiles) : (int)(t % a.m_tiles);
+    if (TRI) {
+        // column tile nt costs nt + 1 K blocks: pair long and short tiles
+        // (N-1, 0, N-2, 1, ...) so that every XCD's contiguous run of tiles holds
+        // a balanced share of the work
+        nt = (nt & 1) ? (nt >> 1) : a.n_tiles - 1 - (nt >> 1);
+    }
 
     int64_t Mrows = a.M;
     if (STORE_Y) { const int64_t k = *a.nrows_d - a.offset; Mrows = k < a.M ? k : a.M; }
@@ -113,7 +133,8 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
 
     uint64_t aw[KC / 64];
     uint4 br[BCH];
-    const int nk = (a.n_pad + KC - 1) / KC;
+    const int nk_full = (a.n_pad + KC - 1) / KC;
+    const int nk = TRI ? min(nk_full, (n0 + BN + KC - 1) / KC) : nk_full;
     // global -> registers for K step kc; columns past n_pad (the tail of the last step) read as 0
 #define EVAL_LOAD_STAGE(kc)                                                                   \
     do {                                                                                      \
@@ -125,6 +146,21 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
         _Pragma("unroll") for (int i_ = 0; i_ < BCH; i_++) {                                  \
             br[i_] = kin_ ? *(const uint4 *)(qsrc + (int64_t)(BROWS * i_) * a.n_pad + (kc) * KC) \
                           : uint4{0u, 0u, 0u, 0u};                                            \
+        }                                                                                     \
+        if (TRI && (kc) * KC + KC > n0) {                                                     \
+            /* diagonal block: keep bytes with k <= j (j = column, k = byte's K index) */     \
+            _Pragma("unroll") for (int i_ = 0; i_ < BCH; i_++) {                              \
+                const int lim_ = n0 + brow + BROWS * i_ - ((kc) * KC + bc16 * 16) + 1;        \
+                uint32_t m_[4];                                                               \
+                _Pragma("unroll") for (int d_ = 0; d_ < 4; d_++) {                            \
+                    const int v_ = min(max(lim_ - 4 * d_, 0), 4);                             \
+                    m_[d_] = v_ >= 4 ? 0xFFFFFFFFu : ((1u << (8 * v_)) - 1u);                 \
+                }                                                                             \
+                br[i_].x &= m_[0];                                                            \
+                br[i_].y &= m_[1];                                                            \
+                br[i_].z &= m_[2];                                                            \
+                br[i_].w &= m_[3];                                                            \
+            }                                                                                 \
         }                                                                                     \
     } while (0)
     // registers -> LDS buffer buf
@@ -214,6 +250,12 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     const int word0 = n0 >> 6;
     if constexpr (EPI == EPI_ROWDOT) {
         const int64_t wgt = plane == 0 ? a.weight0 : 1;
+        int32_t dq[FN];  // this plane's q_jj of the lane's columns
+#pragma unroll
+        for (int ni = 0; ni < FN; ni++) {
+            const int col = n0 + ni * 32 + r32;
+            dq[ni] = qp[(int64_t)col * a.n_pad + col];
+        }
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
 #pragma unroll
@@ -228,9 +270,9 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
 #pragma unroll
                 for (int ni = 0; ni < FN; ni++) {
                     const uint64_t xw = ni < 2 ? xw0 : xw1;
-                    s += ((xw >> (32 * (ni & 1) + r32)) & 1ull) ? acc[mi][ni][e] : 0;
+                    s += ((xw >> (32 * (ni & 1) + r32)) & 1ull) ? 2 * acc[mi][ni][e] - dq[ni] : 0;
                 }
-                // |s| <= 4 * 128 n <= 2^22: the 32-lane sum stays inside int32
+                // |s| <= 4 (2 * 128 n + 128) < 2^24: the 32-lane sum stays inside int32
                 s = row16_sum(s);
                 s += __shfl_xor(s, 16);
                 if (r32 == 0 && row < Mrows && s != 0)
@@ -273,6 +315,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
                         const int32_t xj = (int32_t)((xw >> (32 * (ni & 1) + r32)) & 1ull);
                         const int32_t y2 = 2 * acc[mi][ni][e];
                         const int32_t delta = dg[ni] + (xj ? -y2 : y2);
+                        // local index of column col within its ascent lane: col mod PL
                         a.Y[row * a.n_pad + col] = delta * 256 + 2 * (127 - col % a.keys_pl) + xj;
                     }
                 }
@@ -281,14 +324,15 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     }
 }
 
+// KC = 64 and 128 fit two workgroups per CU (LDS 28 / 48 KB); KC = 256 (90 KB) one.
 template <int EPI, int KC>
-__global__ __launch_bounds__(THR, KC == 128 ? 2 : 1) void eval_kernel(EvalArgs a, int64_t total)
+__global__ __launch_bounds__(THR, KC <= 128 ? 2 : 1) void eval_kernel(EvalArgs a, int64_t total)
 {
     eval_body<EPI, KC>(a, xcd_tile(blockIdx.x, total));
 }
 
 template <int EPI, int KC>
-__global__ __launch_bounds__(THR, KC == 128 ? 2 : 1) void eval_batched(const EvalArgs *args, const int64_t *prefix,
+__global__ __launch_bounds__(THR, KC <= 128 ? 2 : 1) void eval_batched(const EvalArgs *args, const int64_t *prefix,
                                                                       int count, int64_t total)
 {
     const int64_t t = xcd_tile(blockIdx.x, total);
@@ -318,6 +362,7 @@ __global__ __launch_bounds__(256) void eval_init_batched(const EvalArgs *args, c
     eval_init_body(args[i], blockIdx.x - prefix[i]);
 }
 
+// K depth of the Delta-initialisation contractions (Y rows and keys).
 #ifndef EVAL_KC
 #define EVAL_KC 128
 #endif
@@ -364,11 +409,31 @@ int64_t ubqp_yrows_tiles(const EvalArgs &a)
 }
 int64_t ubqp_eval_init_blocks(const EvalArgs &a) { return (a.M + 255) / 256; }
 
-hipError_t ubqp_launch_eval(hipStream_t st, const EvalArgs &a)
+int ubqp_eval_variant_kc(int variant) { return variant / 2 == 0 ? 64 : variant / 2 == 1 ? 128 : 256; }
+
+hipError_t ubqp_launch_eval_v(hipStream_t st, EvalArgs a, int variant)
 {
+    a.order = variant & 1;
     hipLaunchKernelGGL(eval_init, dim3((unsigned)ubqp_eval_init_blocks(a)), dim3(256), 0, st, a);
     const int64_t T = ubqp_eval_tiles(a);
-    hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, EVAL_KC>), dim3((unsigned)T), dim3(THR), 0, st, a, T);
+    switch (ubqp_eval_variant_kc(variant)) {
+    case 64: hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, 64>), dim3((unsigned)T), dim3(THR), 0, st, a, T); break;
+    case 128: hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, 128>), dim3((unsigned)T), dim3(THR), 0, st, a, T); break;
+    default: hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, 256>), dim3((unsigned)T), dim3(THR), 0, st, a, T); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ubqp_launch_eval_rowdot_batch(hipStream_t st, int variant, const EvalArgs *args, const int64_t *prefix,
+                                         int count, int64_t tiles)
+{
+    if (tiles <= 0) return hipSuccess;
+    const dim3 g((unsigned)tiles), b(THR);
+    switch (ubqp_eval_variant_kc(variant)) {
+    case 64: hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, 64>), g, b, 0, st, args, prefix, count, tiles); break;
+    case 128: hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, 128>), g, b, 0, st, args, prefix, count, tiles); break;
+    default: hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, 256>), g, b, 0, st, args, prefix, count, tiles); break;
+    }
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ inline size_t ubqp_align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Offsets of one instance's device state inside its allocation.
 struct InstLayout {
-    size_t seeds, X, f, flips, idx, scal, bestx, stats, part, err, Y, total;
+    size_t seeds, X, f, flips, idx, rank, scal, bestx, stats, part, err, Y, total;
     int64_t S, cap;
 };
 InstLayout ubqp_inst_layout(const ubqp_problem *p, const ubqp_params *pr);
@@ -72,10 +72,16 @@ struct Chunk {
     Table<AscArgs> asc;
 };
 
+struct EvalGroup {         // instances whose row-dot contraction uses one variant
+    int variant;
+    Table<EvalArgs> t;
+};
+
 struct GenTables {
     int count = 0;
     Table<DivArgs> div;
-    Table<EvalArgs> ev, einit;
+    Table<EvalArgs> einit;
+    std::vector<EvalGroup> ev;
     Table<ScreenArgs> scr;
     Table<SelArgs> sel_cand, sel_seed;  // same arguments, two prefixes
     Table<SelArgs> init;                // generation-0 seeds of the joining instances

@@ -27,6 +27,7 @@ InstLayout ubqp_inst_layout(const ubqp_problem *p, const ubqp_params *pr)
     L.f = take((size_t)M * 8);
     L.flips = take((size_t)M * 4);
     L.idx = take((size_t)M * 4);
+    L.rank = take((size_t)M * 4);
     L.scal = take(sizeof(ubqp_scal));
     L.bestx = take((size_t)W * 8);
     L.stats = take((size_t)pr->G * 5 * 8);
@@ -57,15 +58,20 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
         d.X = X;
         d.total = pr.M * p->W;
         div.add(d, ubqp_div_blocks(d));
-        const EvalArgs ea = ubqp_eval_args(p, X, pr.M, f);
+        EvalArgs ea = ubqp_eval_args(p, X, pr.M, f);
         einit.add(ea, ubqp_eval_init_blocks(ea));
-        ev.add(ea, ubqp_eval_tiles(ea));
+        const int variant = ubqp_eval_variant_for(p, pr.M);
+        ea.order = variant & 1;
+        size_t gi = 0;
+        while (gi < ev.size() && ev[gi].variant != variant) gi++;
+        if (gi == ev.size()) ev.push_back(EvalGroup{variant, {}});
+        ev[gi].t.add(ea, ubqp_eval_tiles(ea));
         const ScreenArgs sa = ubqp_screen_args(f, pr.M, pr.lam_num, pr.lam_den, idx, &sc->npass, sc->sum_max,
                                                r.at<void>(L.part));
         scr.add(sa, sa.nblk);
         if (r.dump) has_dump = true;
-        const SelArgs sl = ubqp_sel_args(p->n, pr.M, L.S, pr.run_seed, X, f, flips, idx, sc, r.at<uint64_t>(L.bestx),
-                                         seeds, r.at<int64_t>(L.stats),
+        const SelArgs sl = ubqp_sel_args(p->n, pr.M, L.S, pr.run_seed, X, f, flips, idx, r.at<int32_t>(L.rank), sc,
+                                         r.at<uint64_t>(L.bestx), seeds, r.at<int64_t>(L.stats),
                                          (pr.flags & UBQP_DERIV_START) ? p->deriv_x : nullptr, r.dump);
         sel_cand.add(sl, ubqp_cand_blocks(sl));
         sel_seed.add(sl, ubqp_seed_blocks(sl));
@@ -98,7 +104,7 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
     host.clear();
     div.stage(host);
     einit.stage(host);
-    ev.stage(host);
+    for (EvalGroup &g : ev) g.t.stage(host);
     scr.stage(host);
     sel_cand.stage(host);
     sel_seed.stage(host);
@@ -113,7 +119,7 @@ void GenTables::bind(char *dev)
 {
     div.bind(dev);
     einit.bind(dev);
-    ev.bind(dev);
+    for (EvalGroup &g : ev) g.t.bind(dev);
     scr.bind(dev);
     sel_cand.bind(dev);
     sel_seed.bind(dev);
@@ -144,7 +150,8 @@ hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t 
     Q(ubqp_launch_diversify_batch(st, t.div.d_args, t.div.d_pre, n, t.div.total()));
     MARK(1);
     Q(ubqp_launch_eval_init_batch(st, t.einit.d_args, t.einit.d_pre, n, t.einit.total()));
-    Q(ubqp_launch_eval_batch(st, UBQP_EPI_ROWDOT, t.ev.d_args, t.ev.d_pre, n, t.ev.total()));
+    for (const EvalGroup &g : t.ev)
+        Q(ubqp_launch_eval_rowdot_batch(st, g.variant, g.t.d_args, g.t.d_pre, g.t.count(), g.t.total()));
     MARK(2);
     if (t.has_dump) Q(ubqp_launch_dump_batch(st, t.sel_cand.d_args, t.sel_cand.d_pre, n, t.sel_cand.total()));
     Q(ubqp_launch_screen_batch(st, t.scr.d_args, t.scr.d_pre, n, t.scr.total()));
@@ -213,6 +220,8 @@ int plan_create(ubqp_ctx *ctx, int count, const ubqp_problem *const *probs, cons
             return ubqp_fail(ctx, UBQP_EINVAL, "G differs between instances (%d vs %d)", params[i].G, params[0].G);
     }
     UBQP_TRY(ubqp_set_device(ctx));
+    for (int i = 0; i < count; i++)
+        if (params[i].flags & UBQP_AUTOTUNE) UBQP_TRY(ubqp_tune_eval_internal(ctx, probs[i], params[i].M, nullptr, nullptr));
     ubqp_plan *pl = new (std::nothrow) ubqp_plan();
     if (!pl) return ubqp_fail(ctx, UBQP_ENOMEM, "host allocation");
     pl->ctx = ctx;

@@ -4,8 +4,9 @@
 // layout by kernels, so the host does no O(n^2) work:
 //   check: symmetry, range [-32768, 32767], and whether every entry fits int8;
 //   build: int8 planes [planes][n_pad][n_pad] (one plane, or hi = q >> 8 and
-//          lo = (q & 255) - 128), the ascent matrix (Q with a zero diagonal:
-//          int8 [n_pad][ncol_a] or int16 [n_pad][n_pad]), zero padded;
+//          lo = (q & 255) - 128), the ascent matrix (Q with a zero diagonal,
+//          int8 or int16 [n_pad][ncol_a], ncol_a = 1024 ceil(n_pad / 1024)),
+//          zero padded;
 //   rows:  q_ii and the first-derivative start x_i = [sum_j q_ij > 0].
 // The pieces are queued on a caller's stream so that the request server can
 // upload one problem while others compute.
@@ -36,23 +37,48 @@ __global__ void check_init(ubqp_check_flags *fl)
     fl->first[0] = fl->first[1] = ~0ull;
 }
 
-__global__ __launch_bounds__(THR) void check_kernel(const void *q, int elem, int32_t n, ubqp_check_flags *fl)
+// 32 x 32 tiles (I, J), I <= J: tile (I, J) and its mirror (J, I) are read
+// row-wise (coalesced), the mirror is transposed through LDS, and q_ij is compared
+// with q_ji for j > i; every entry of both tiles is range-checked.
+constexpr int CT = 32;
+__global__ __launch_bounds__(CT * 8) void check_kernel(const void *q, int elem, int32_t n, ubqp_check_flags *fl)
 {
-    const int64_t k = (int64_t)blockIdx.x * THR + threadIdx.x;
-    const int64_t nn = (int64_t)n * n;
-    if (k >= nn) return;
-    const int64_t i = k / n, j = k - i * n;
-    const int32_t v = load_q(q, elem, k);
+    __shared__ int32_t mir[CT][CT + 1];
+    const int I = blockIdx.y, J = blockIdx.x;
+    if (I > J) return;
+    const int tx = threadIdx.x & (CT - 1), ty = threadIdx.x / CT;
     uint32_t b = 0;
-    if (j > i && v != load_q(q, elem, j * n + i)) {
-        b |= UBQP_CHECK_ASYM;
-        atomicMin(&fl->first[0], (unsigned long long)k);
+    unsigned long long first_asym = ~0ull, first_range = ~0ull;
+    for (int r = ty; r < CT; r += 8) {
+        const int64_t i = (int64_t)J * CT + r, j = (int64_t)I * CT + tx;  // mirror tile entry (i, j)
+        if (i < n && j < n) {
+            const int32_t v = load_q(q, elem, i * n + j);
+            mir[tx][r] = v;
+            if (v < -32768 || v > 32767) {
+                b |= UBQP_CHECK_RANGE;
+                first_range = min(first_range, (unsigned long long)(i * n + j));
+            }
+            if (v < -128 || v > 127) b |= UBQP_CHECK_WIDE;
+        }
     }
-    if (v < -32768 || v > 32767) {
-        b |= UBQP_CHECK_RANGE;
-        atomicMin(&fl->first[1], (unsigned long long)k);
+    __syncthreads();
+    for (int r = ty; r < CT; r += 8) {
+        const int64_t i = (int64_t)I * CT + r, j = (int64_t)J * CT + tx;
+        if (i < n && j < n) {
+            const int32_t v = load_q(q, elem, i * n + j);
+            if (v < -32768 || v > 32767) {
+                b |= UBQP_CHECK_RANGE;
+                first_range = min(first_range, (unsigned long long)(i * n + j));
+            }
+            if (v < -128 || v > 127) b |= UBQP_CHECK_WIDE;
+            if (j > i && v != mir[r][tx]) {  // mir[r][tx] = q[J*CT + tx][I*CT + r] = q_ji
+                b |= UBQP_CHECK_ASYM;
+                first_asym = min(first_asym, (unsigned long long)(i * n + j));
+            }
+        }
     }
-    if (v < -128 || v > 127) b |= UBQP_CHECK_WIDE;
+    if (b & UBQP_CHECK_ASYM) atomicMin(&fl->first[0], first_asym);
+    if (b & UBQP_CHECK_RANGE) atomicMin(&fl->first[1], first_range);
     if (b) atomicOr(&fl->bits, b);
 }
 
@@ -75,10 +101,11 @@ __global__ __launch_bounds__(THR) void build_kernel(const void *q, int elem, int
         }
     }
     const int32_t a = (i == j) ? 0 : v;
-    if (narrow) {
-        if (j < ncol_a) ((int8_t *)qa)[i * ncol_a + j] = (int8_t)a;
-    } else if (j < n_pad) {
-        ((int16_t *)qa)[i * n_pad + j] = (int16_t)a;
+    if (j < ncol_a) {
+        if (narrow)
+            ((int8_t *)qa)[i * ncol_a + j] = (int8_t)a;
+        else
+            ((int16_t *)qa)[i * ncol_a + j] = (int16_t)a;
     }
 }
 
@@ -113,7 +140,7 @@ void ubqp_problem_geometry(ubqp_problem *p, int32_t n, int32_t planes)
     p->weight0 = planes == 1 ? 1 : 256;
     p->bias = planes == 1 ? 0 : 128;
     const int64_t np = p->n_pad;
-    p->ncol_a = planes == 1 ? (int32_t)((np + 1023) / 1024 * 1024) : (int32_t)np;
+    p->ncol_a = (int32_t)((np + 1023) / 1024 * 1024);
 }
 
 size_t ubqp_problem_bytes(const ubqp_problem *p)
@@ -140,9 +167,9 @@ void ubqp_problem_bind(ubqp_problem *p, char *mem)
 
 hipError_t ubqp_queue_problem_check(hipStream_t st, const void *stage, int elem, int32_t n, ubqp_check_flags *fl)
 {
-    const int64_t nn = (int64_t)n * n;
+    const unsigned T = (unsigned)((n + CT - 1) / CT);
     hipLaunchKernelGGL(check_init, dim3(1), dim3(1), 0, st, fl);
-    hipLaunchKernelGGL(check_kernel, dim3((unsigned)((nn + THR - 1) / THR)), dim3(THR), 0, st, stage, elem, n, fl);
+    hipLaunchKernelGGL(check_kernel, dim3(T, T), dim3(CT * 8), 0, st, stage, elem, n, fl);
     return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ __device__ void incumbent_body(const SelArgs &a)
         const int32_t c = a.idx[p];
         const int64_t v = a.f[c];
         fl += a.flips[c];
+        a.rank[p] = 0;
         if (v > bf || (v == bf && c < bc)) { bf = v; bc = c; }
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -107,27 +108,44 @@ __device__ void incumbent_body(const SelArgs &a)
         for (int w = threadIdx.x; w < a.W; w += THR) a.best_x[w] = a.X[(int64_t)winner * a.W + w];
 }
 
-// Rank of each passer by (f desc, index asc); the top S-1 become seeds 1..S-1.
+// Rank of each passer by (f desc, index asc): the instance's ceil(M / 256)
+// blocks split into E = ceil(P / 256) passer chunks times as many slices of the
+// comparison range as fit; each block adds its partial counts to rank[] (zeroed
+// by the incumbent kernel).
 __device__ void rank_body(const SelArgs &a, int64_t bid)
 {
     __shared__ int64_t tf[THR];
     const int64_t P = a.scal->npass;
-    const int64_t p0 = bid * THR;
-    if (p0 >= P) return;
-    const int64_t p = p0 + threadIdx.x;
+    const int64_t E = (P + THR - 1) / THR;
+    if (E == 0) return;
+    const int64_t nblk = (a.M + THR - 1) / THR;
+    const int64_t slices = nblk / E > 0 ? nblk / E : 1;
+    if (bid >= E * slices) return;
+    const int64_t p = (bid % E) * THR + threadIdx.x, slice = bid / E;
+    const int64_t lo = P * slice / slices, hi = P * (slice + 1) / slices;
     const int64_t fp = p < P ? a.f[a.idx[p]] : 0;
-    int64_t r = 0;
-    for (int64_t base = 0; base < P; base += THR) {
+    int32_t r = 0;
+    for (int64_t base = lo; base < hi; base += THR) {
         __syncthreads();
-        if (base + threadIdx.x < P) tf[threadIdx.x] = a.f[a.idx[base + threadIdx.x]];
+        if (base + threadIdx.x < hi) tf[threadIdx.x] = a.f[a.idx[base + threadIdx.x]];
         __syncthreads();
-        const int64_t lim = P - base < THR ? P - base : THR;
+        const int64_t lim = hi - base < THR ? hi - base : THR;
         for (int64_t q = 0; q < lim; q++) {
             const int64_t fq = tf[q];
             r += (fq > fp) || (fq == fp && base + q < p);
         }
     }
-    if (p < P && r < a.S - 1) {
+    if (p < P && r) atomicAdd(&a.rank[p], r);
+}
+
+// The top S-1 passers become seeds 1..S-1.
+__device__ void place_body(const SelArgs &a, int64_t bid)
+{
+    const int64_t P = a.scal->npass;
+    const int64_t p = bid * THR + threadIdx.x;
+    if (p >= P) return;
+    const int64_t r = a.rank[p];
+    if (r < a.S - 1) {
         const uint64_t *src = a.X + (int64_t)a.idx[p] * a.W;
         uint64_t *dst = a.seeds + (1 + r) * a.W;
         for (int w = 0; w < a.W; w++) dst[w] = src[w];
@@ -161,6 +179,7 @@ __global__ __launch_bounds__(THR) void seed_init_kernel(SelArgs a) { seed_init_b
 BATCHED(seed_init_b, seed_init_body)
 BATCHED(dump_b, dump_body)
 BATCHED(rank_b, rank_body)
+BATCHED(place_b, place_body)
 BATCHED(seed_fill_b, seed_fill_body)
 #undef BATCHED
 
@@ -178,10 +197,11 @@ __global__ void advance_b(const SelArgs *args, int count)
 }  // namespace
 
 SelArgs ubqp_sel_args(int32_t n, int64_t M, int64_t S, uint64_t run_seed, const uint64_t *X, const int64_t *f,
-                      const int32_t *flips, const int32_t *idx, ubqp_scal *scal, uint64_t *best_x, uint64_t *seeds,
-                      int64_t *stats, const uint64_t *deriv_x, int64_t *f_dump)
+                      const int32_t *flips, const int32_t *idx, int32_t *rank, ubqp_scal *scal, uint64_t *best_x,
+                      uint64_t *seeds, int64_t *stats, const uint64_t *deriv_x, int64_t *f_dump)
 {
     SelArgs a{};
+    a.rank = rank;
     a.n = n;
     a.W = (n + 63) / 64;
     a.M = M;
@@ -228,6 +248,7 @@ hipError_t ubqp_launch_select_batch(hipStream_t st, const SelArgs *args, const i
 {
     hipLaunchKernelGGL(incumbent_b, dim3(count), dim3(THR), 0, st, args, count);
     hipLaunchKernelGGL(rank_b, dim3((unsigned)cand_blocks), dim3(THR), 0, st, args, cand_prefix, count);
+    hipLaunchKernelGGL(place_b, dim3((unsigned)cand_blocks), dim3(THR), 0, st, args, cand_prefix, count);
     hipLaunchKernelGGL(seed_fill_b, dim3((unsigned)seed_blocks), dim3(THR), 0, st, args, seed_prefix, count);
     hipLaunchKernelGGL(advance_b, dim3((count + 63) / 64), dim3(64), 0, st, args, count);
     return hipGetLastError();

@@ -20,7 +20,7 @@ struct ubqp_ctx {
     std::string err;
     // Growable device workspace of the step-level entry points, one buffer per slot
     // (a multi-start run owns its own device state).
-    enum Slot { WS_PARTIALS, WS_Y, WS_STAGE, WS_COUNT };
+    enum Slot { WS_PARTIALS, WS_Y, WS_STAGE, WS_TUNE, WS_COUNT };
     void *ws[WS_COUNT] = {};
     size_t ws_bytes[WS_COUNT] = {};
     int32_t *err_flag = nullptr;  // device int32: kernel-side checks (ascent safety cap)
@@ -31,8 +31,8 @@ struct ubqp_problem {
     void *mem = nullptr;       // owned device block holding the arrays below (null: a view into server memory)
     int32_t n = 0, n_pad = 0, W = 0, planes = 1;
     int8_t *q = nullptr;       // [planes][n_pad][n_pad]: plane 0 (hi or the only plane), plane 1 (lo)
-    void *qa = nullptr;        // ascent matrix, zero diagonal: int8 [n_pad][ncol_a] (planes 1) or int16 [n_pad][n_pad]
-    int32_t ncol_a = 0;        // columns of the int8 ascent matrix: 1024 * ceil(n_pad / 1024)
+    void *qa = nullptr;        // ascent matrix, zero diagonal: int8 (planes 1) or int16 (planes 2) [n_pad][ncol_a]
+    int32_t ncol_a = 0;        // columns of the ascent matrix: 1024 * ceil(n_pad / 1024)
     int32_t *diag = nullptr;   // [n_pad] q_ii (0 in the padding)
     uint64_t *deriv_x = nullptr;  // [W] first-derivative starting solution
     int64_t weight0 = 1;       // weight of plane 0 (256 when split)
@@ -137,6 +137,8 @@ struct EvalArgs {            // int8 matrix-core contraction Y = X Q and its epi
     const int32_t *diag;     // keys: q_jj
     int32_t keys_pl;         // keys: columns per lane of the ascent (16 NB)
     int64_t bias;            // eval_init: f starts at bias * popcount(x)^2
+    int32_t order;           // tile order: 0 n-tile-major, 1 m-tile-major (an eval variant choice)
+    int32_t pad_;
 };
 
 struct ScreenArgs {          // exact T(lambda) screening
@@ -150,8 +152,8 @@ struct ScreenArgs {          // exact T(lambda) screening
 };
 
 struct AscArgs {             // steepest 1-flip ascent
-    const void *qa;          // zero diagonal: int8 [n_pad][ncol_a] or int16 [n_pad][n_pad]
-    int32_t ncol_a;          // columns of the int8 ascent matrix (1024 NB)
+    const void *qa;          // zero diagonal: int8 or int16 [n_pad][ncol_a]
+    int32_t ncol_a;          // columns of the ascent matrix (1024 NB)
     const int32_t *diag;
     int32_t n, n_pad, W, planes;
     int64_t weight0, bias;
@@ -176,6 +178,7 @@ struct SelArgs {             // incumbent update, next seeds, statistics, genera
     const int64_t *f;
     const int32_t *flips;
     const int32_t *idx;
+    int32_t *rank;           // [M] scratch: rank of each passer
     ubqp_scal *scal;
     uint64_t *best_x, *seeds;
     int64_t *stats;
@@ -207,12 +210,25 @@ EvalArgs ubqp_yrows_args(const ubqp_problem *p, const uint64_t *X, int64_t x_row
 int64_t ubqp_eval_tiles(const EvalArgs &a);
 int64_t ubqp_yrows_tiles(const EvalArgs &a);
 int64_t ubqp_eval_init_blocks(const EvalArgs &a);
-hipError_t ubqp_launch_eval(hipStream_t st, const EvalArgs &a);  // eval_init, then the row-dot contraction
 hipError_t ubqp_launch_yrows(hipStream_t st, const EvalArgs &a);
 hipError_t ubqp_launch_eval_init_batch(hipStream_t st, const EvalArgs *args, const int64_t *prefix, int count,
                                        int64_t blocks);
 hipError_t ubqp_launch_eval_batch(hipStream_t st, int epilogue, const EvalArgs *args, const int64_t *prefix,
                                   int count, int64_t tiles);
+
+// Variants of the row-dot contraction (the autotuner's choices): variant v stages
+// K ubqp_eval_variant_kc(v) = 64, 128 or 256 deep (v / 2 = 0, 1, 2) and orders the
+// tiles n-tile-major (v even) or m-tile-major (v odd).
+#define UBQP_EVAL_DEFAULT_VARIANT 2
+int ubqp_eval_variant_kc(int variant);
+hipError_t ubqp_launch_eval_v(hipStream_t st, EvalArgs a, int variant);  // eval_init + contraction
+// The contraction alone, batched; every args[i].order must equal variant & 1.
+hipError_t ubqp_launch_eval_rowdot_batch(hipStream_t st, int variant, const EvalArgs *args, const int64_t *prefix,
+                                         int count, int64_t tiles);
+// Variant the autotuner chose for (p, M), or UBQP_EVAL_DEFAULT_VARIANT if it has not run.
+int ubqp_eval_variant_for(const ubqp_problem *p, int64_t M);
+// Tune (p, M) unless cached; synchronous on ctx->stream.
+int ubqp_tune_eval_internal(ubqp_ctx *ctx, const ubqp_problem *p, int64_t M, int32_t *variant, double *ms);
 
 int32_t ubqp_screen_blocks(int64_t M);
 size_t ubqp_screen_partials_bytes(int64_t M);
@@ -234,8 +250,8 @@ hipError_t ubqp_launch_ascent_batch(hipStream_t st, int planes, int nb, const As
                                     int count, int64_t waves);
 
 SelArgs ubqp_sel_args(int32_t n, int64_t M, int64_t S, uint64_t run_seed, const uint64_t *X, const int64_t *f,
-                      const int32_t *flips, const int32_t *idx, ubqp_scal *scal, uint64_t *best_x, uint64_t *seeds,
-                      int64_t *stats, const uint64_t *deriv_x, int64_t *f_dump);
+                      const int32_t *flips, const int32_t *idx, int32_t *rank, ubqp_scal *scal, uint64_t *best_x,
+                      uint64_t *seeds, int64_t *stats, const uint64_t *deriv_x, int64_t *f_dump);
 int64_t ubqp_seed_blocks(const SelArgs &a);
 int64_t ubqp_cand_blocks(const SelArgs &a);
 hipError_t ubqp_launch_seed_init(hipStream_t st, const SelArgs &a);
@@ -243,6 +259,7 @@ hipError_t ubqp_launch_seed_init_batch(hipStream_t st, const SelArgs *args, cons
                                        int64_t seed_blocks);
 hipError_t ubqp_launch_dump_batch(hipStream_t st, const SelArgs *args, const int64_t *cand_prefix, int count,
                                   int64_t cand_blocks);
-// incumbent update + statistics, ranking into seeds 1.., seed 0 and random fill, generation counter
+// incumbent update + statistics, ranking and placement into seeds 1.., seed 0 and random fill,
+// generation counter
 hipError_t ubqp_launch_select_batch(hipStream_t st, const SelArgs *args, const int64_t *cand_prefix,
                                     int64_t cand_blocks, const int64_t *seed_prefix, int64_t seed_blocks, int count);

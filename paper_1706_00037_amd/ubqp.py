@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libubqp.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ubqp.h")
 
 UBQP_OK, UBQP_EINVAL, UBQP_ERANGE, UBQP_EASYM, UBQP_ENOMEM, UBQP_EDEVICE = 0, -1, -2, -3, -4, -5
-UBQP_DERIV_START, UBQP_TIMING, UBQP_NO_GRAPH = 1, 2, 4
+UBQP_DERIV_START, UBQP_TIMING, UBQP_NO_GRAPH, UBQP_AUTOTUNE = 1, 2, 4, 8
+UBQP_EVAL_VARIANTS = 6
 PHASES = ("diversify", "eval", "screen", "ascent", "select")
 MAX_N, MAX_M, MAX_H = 8192, 1 << 22, 256
 INT64_MIN = -(1 << 63)
@@ -73,6 +74,8 @@ def load():
         "ubqp_problem_info": [P, P, P, P],
         "ubqp_diversify": [P, i32, P, i64, i32, P, i64],
         "ubqp_eval": [P, P, P, i64, P],
+        "ubqp_eval_variant": [P, P, P, i64, P, i32],
+        "ubqp_tune_eval": [P, P, i64, ctypes.POINTER(i32), P],
         "ubqp_screen": [P, P, i64, i32, i32, P, P, P],
         "ubqp_ascent": [P, P, P, i64, P, P, i64, P, i32, P],
         "ubqp_multistart": [P, P, ctypes.POINTER(Params), P, ctypes.POINTER(Result)],
@@ -386,6 +389,19 @@ class Context:
         M = X.numel() // prob.W if M is None else M
         self._call("ubqp_eval", self.h, prob.h, self._t(X, torch.int64, M * prob.W, "X"), M,
                    self._t(f, torch.int64, M, "f"))
+
+    def eval_variant(self, prob: Problem, X, f, variant: int, M=None):
+        torch = self.torch
+        M = X.numel() // prob.W if M is None else M
+        self._call("ubqp_eval_variant", self.h, prob.h, self._t(X, torch.int64, M * prob.W, "X"), M,
+                   self._t(f, torch.int64, M, "f"), variant)
+
+    def tune_eval(self, prob: Problem, M: int):
+        """(chosen variant, milliseconds of each variant) for prob at M candidates."""
+        v = ctypes.c_int32()
+        ms = np.zeros(UBQP_EVAL_VARIANTS, np.float64)
+        self._call("ubqp_tune_eval", self.h, prob.h, M, ctypes.byref(v), ms.ctypes.data_as(ctypes.c_void_p))
+        return int(v.value), [float(t) for t in ms]
 
     def screen(self, f, lam_num, lam_den, idx, npass, sum_max, M=None):
         torch = self.torch

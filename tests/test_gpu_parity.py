@@ -31,6 +31,41 @@ def host_u64(t):
     return t.cpu().numpy().view(np.uint64)
 
 
+# -------------------------------------------------------- problem upload ----
+
+@pytest.mark.parametrize("n", [2, 31, 33, 100, 257])
+@pytest.mark.parametrize("dt", [np.int8, np.int16, np.int32])
+def test_problem_upload_reports_first_asymmetry(ctx, n, dt):
+    """The device check names the first asymmetric entry (row-major, upper triangle),
+    whichever side of the diagonal was changed."""
+    from paper_1706_00037_amd import ubqp
+    Q = make_instance(n, 0.5, -100, 100, 50 + n).astype(dt)
+    pairs = [(n // 2, n - 1), (0, n - 1)] if n > 2 else [(0, 1)]
+    B = Q.copy()
+    for i, j in pairs:
+        B[j, i] = B[i, j] + 1                 # change the lower side
+    i0, j0 = min(pairs)
+    with pytest.raises(ubqp.UbqpError) as e:
+        ctx.problem(B)
+    assert e.value.code == ubqp.UBQP_EASYM and f"q[{i0}][{j0}]" in str(e.value)
+    prob = ctx.problem(Q)                     # the unchanged matrix still uploads
+    assert prob.planes == 1
+
+
+@pytest.mark.parametrize("n", [1, 40, 129])
+def test_problem_upload_range_and_planes(ctx, n):
+    from paper_1706_00037_amd import ubqp
+    Q = make_instance(n, 0.5, -100, 100, 60 + n)
+    R = Q.copy()
+    R[n - 1, 0] = R[0, n - 1] = 40000         # symmetric but outside int16
+    with pytest.raises(ubqp.UbqpError) as e:
+        ctx.problem(R)
+    assert e.value.code == ubqp.UBQP_ERANGE and f"q[0][{n - 1}]" in str(e.value)
+    W = Q.copy()
+    W[n - 1, n - 1] = -129                    # one wide entry: two planes
+    assert ctx.problem(W).planes == 2 and ctx.problem(Q).planes == 1
+
+
 # ----------------------------------------------------------------- eval ----
 
 EVAL_CASES = [

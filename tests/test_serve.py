@@ -133,12 +133,19 @@ def test_mix_matches_oracle(ctx, ub):
 
 
 def test_admission_by_footprint_and_slots(ctx, ub):
-    """A pool that holds two requests at a time: never more than two run, all
-    finish, results unchanged.  max_active = 1 runs them one at a time."""
-    cases = [_make(k, c) for k, c in enumerate(_requests()) if 100 <= c[0] <= 1100]
-    fp = max(ub.request_footprint(Q.shape[0], Q.dtype.itemsize, pr) for Q, pr in cases)
-    alone = [_alone(ctx, Q, pr) for Q, pr in cases]
-    for pool, act, cap in [(2 * fp + 4096, 16, 2), (1 << 30, 1, 1)]:
+    """Equal requests and a pool that holds two of them: never more than two run.
+    Mixed requests in a small pool: the pool bound holds.  max_active = 1 runs one
+    at a time.  Every result equals the solve alone."""
+    same = []
+    for k in range(5):
+        Q = make_instance(600, 0.3, -100, 100, 9300 + k).astype(np.int8)
+        same.append((Q, dict(M=1000, H=10, lam_num=1, lam_den=2, G=3, max_flips=0, flags=0, run_seed=70 + k)))
+    mixed = [_make(k, c) for k, c in enumerate(_requests()) if 100 <= c[0] <= 1100]
+    fp_same = ub.request_footprint(600, 1, same[0][1])
+    fp_mixed = max(ub.request_footprint(Q.shape[0], Q.dtype.itemsize, pr) for Q, pr in mixed)
+    for cases, pool, act, cap in [(same, 2 * fp_same + 4096, 16, 2), (mixed, 2 * fp_mixed + 4096, 16, None),
+                                  (mixed, 1 << 30, 1, 1)]:
+        alone = [_alone(ctx, Q, pr) for Q, pr in cases]
         srv = ub.Server(ctx, pool_bytes=pool, max_active=act)
         try:
             ids = [srv.submit(Q, **pr) for Q, pr in cases]
@@ -146,7 +153,9 @@ def test_admission_by_footprint_and_slots(ctx, ub):
             st = srv.stats()
         finally:
             srv.close()
-        assert st["max_running"] <= cap and st["pool_high"] <= pool
+        assert st["pool_high"] <= pool and st["max_running"] <= act
+        if cap is not None:
+            assert st["max_running"] <= cap, (st, cap)
         for k, i in enumerate(ids):
             _same(got[i], alone[k], (pool, act, k))
 
