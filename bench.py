@@ -38,6 +38,11 @@ HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0      # dense int8 matrix-core peak, TOP/s
 VALU_INT32_TOPS = 39.3       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, int32 ops/s / 1e12
 PAPER_TABLE1_S = {2500: 0.7, 5000: 2.0, 6000: 3.0, 7000: 3.5}   # GPU seconds per 1000 evals
+# Memory traffic per launch of the two main kernels at this workload, from the two
+# counter passes summarised in profiles/counters_n7000_M16384.md (FETCH_SIZE and
+# WRITE_SIZE, calibrated against a 1 GiB device copy).  Valid for the kernels as
+# they were when the counters were taken; set to None when a kernel changes.
+TRAFFIC_GB = {"ascent": 8.81 + 0.004, "eval": 0.5617 + 0.0288}
 
 
 def log(msg):
@@ -325,25 +330,29 @@ def main():
     log(f"[bench] eval alone {eval_ms:.3f} ms: {useful_ops / eval_ms / 1e9:.1f} TOP/s useful")
 
     # ---- roofline of the dominant phase ------------------------------------------
-    dom = max(phase_mean, key=phase_mean.get)
+    dom = max((k for k in phase_mean if k != "ascent_kernel"), key=phase_mean.get)
     if dom == "eval":
         t_ms = phase_mean["eval"]
         ach = useful_ops / (t_ms * 1e-3) / 1e12
-        roof = dict(kernel="eval_kernel (int8 MFMA Y = XQ, fused row dot)", bound="mfma", achieved=ach,
-                    peak=INT8_PEAK_TOPS, unit="TFLOP/s", frac=ach / INT8_PEAK_TOPS, traffic=None,
+        roof = dict(kernel="eval_batched<0,128> (int8 MFMA, lower triangle, fused row dot)", bound="mfma",
+                    achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s", frac=ach / INT8_PEAK_TOPS,
+                    traffic=TRAFFIC_GB["eval"], traffic_unit="GB per launch (HBM/fabric, calibrated counters)",
                     algorithmic="2 n^2 int8 ops per candidate x M candidates per launch",
                     avg_launch_ms=t_ms)
     else:
-        t_ms = phase_mean[dom]
-        # ascent: every flip streams one row of the ascent matrix, n int8 entries,
-        # from the memory system (Infinity Cache / HBM); Delta stays in registers
+        # the ascent kernel alone (its launches in a generation, bracketed by stream
+        # events on the launch stream): every flip streams one row of the ascent
+        # matrix, n int8 entries, from the memory system; Delta stays in registers
+        t_ms = phase_mean["ascent_kernel"]
         byts = flips_mean * n
         ach = byts / (t_ms * 1e-3) / 1e9
         alu = flips_mean * n * 2.5 / (t_ms * 1e-3) / 1e12
-        roof = dict(kernel=f"{dom} phase (ascent_i8_batched, with its Delta-initialisation contraction)",
+        roof = dict(kernel="ascent_i8_batched<7> (steepest 1-flip ascent of every passer)",
                     bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                    traffic=None, algorithmic="n bytes of Q per flip x flips of the generation",
-                    avg_launch_ms=t_ms, flips_per_s=flips_mean / (t_ms * 1e-3),
+                    traffic=TRAFFIC_GB["ascent"], traffic_unit="GB per launch (HBM/fabric, calibrated counters)",
+                    algorithmic="n bytes of Q per flip x flips of the generation",
+                    algorithmic_gb_per_launch=byts / 1e9, avg_launch_ms=t_ms,
+                    phase_ms_with_delta_init=phase_mean[dom], flips_per_s=flips_mean / (t_ms * 1e-3),
                     valu_tops=alu, valu_frac=alu / VALU_INT32_TOPS)
 
     # ---- the paper's Table 1 replica: 1000 random solutions --------------------------
@@ -407,8 +416,10 @@ def main():
         "passers_per_gen": P_mean,
         "flips_per_gen": flips_mean,
         "eval_only": {"ms": eval_ms, "evals_per_s": M / (eval_ms * 1e-3),
-                      "useful_tops": useful_ops / eval_ms / 1e9, "executed_tops": exec_ops / eval_ms / 1e9,
-                      "frac_int8_peak": useful_ops / eval_ms / 1e9 / INT8_PEAK_TOPS},
+                      "useful_tops": useful_ops / eval_ms / 1e9, "dense_padded_tops": exec_ops / eval_ms / 1e9,
+                      "frac_int8_peak": useful_ops / eval_ms / 1e9 / INT8_PEAK_TOPS,
+                      "executed_lower_triangle_tops": useful_ops / 2 / eval_ms / 1e9,
+                      "traffic_gb_per_launch": TRAFFIC_GB["eval"]},
         "e1_replica": e1_rep,
         "batched": batched,
         "serving": serving,

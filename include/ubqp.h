@@ -64,7 +64,8 @@ extern "C" {
 #define UBQP_PHASE_SCREEN 2
 #define UBQP_PHASE_ASCENT 3 /* Delta initialisation and ascent of all passers */
 #define UBQP_PHASE_SELECT 4
-#define UBQP_PHASES 5
+#define UBQP_PHASE_ASCENT_KERNEL 5 /* the ascent kernels alone (a part of UBQP_PHASE_ASCENT) */
+#define UBQP_PHASES 6
 
 typedef struct ubqp_ctx ubqp_ctx;         /* library-owned: device, stream, workspace */
 typedef struct ubqp_problem ubqp_problem; /* library-owned: Q resident on the device  */
@@ -94,7 +95,8 @@ typedef struct {
     double *gen_ms_host;    /* out, G: milliseconds from the start of the run to the end   */
                             /*   of each generation, measured with stream events           */
     double *phase_ms_host;  /* out, G x UBQP_PHASES: milliseconds of each phase (runs      */
-                            /*   created with UBQP_TIMING; left untouched otherwise)       */
+                            /*   created with UBQP_TIMING; left untouched otherwise); the  */
+                            /*   first five partition the generation                       */
 } ubqp_result;
 
 typedef struct ubqp_run ubqp_run;      /* library-owned: the device state of one multi-start run */

@@ -46,7 +46,8 @@ __global__ __launch_bounds__(THR) void diversify_kernel(DivArgs a) { diversify_b
 __global__ __launch_bounds__(THR) void diversify_batched(const DivArgs *args, const int64_t *prefix, int count)
 {
     const int i = ubqp_find_inst(prefix, count, blockIdx.x);
-    diversify_body(args[i], blockIdx.x - prefix[i]);
+    const DivArgs a = args[i];  // a local copy: fields stay in registers across stores
+    diversify_body(a, blockIdx.x - prefix[i]);
 }
 
 }  // namespace

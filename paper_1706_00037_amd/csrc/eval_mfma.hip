@@ -337,7 +337,8 @@ __global__ __launch_bounds__(THR, KC <= 128 ? 2 : 1) void eval_batched(const Eva
 {
     const int64_t t = xcd_tile(blockIdx.x, total);
     const int i = ubqp_find_inst(prefix, count, t);
-    eval_body<EPI, KC>(args[i], t - prefix[i]);
+    const EvalArgs a = args[i];  // a local copy: fields stay in registers across stores
+    eval_body<EPI, KC>(a, t - prefix[i]);
 }
 
 // f[c] = bias * popcount(X_c)^2 (the constant part of the split planes) or 0.
@@ -359,7 +360,8 @@ __global__ __launch_bounds__(256) void eval_init(EvalArgs a) { eval_init_body(a,
 __global__ __launch_bounds__(256) void eval_init_batched(const EvalArgs *args, const int64_t *prefix, int count)
 {
     const int i = ubqp_find_inst(prefix, count, blockIdx.x);
-    eval_init_body(args[i], blockIdx.x - prefix[i]);
+    const EvalArgs a = args[i];
+    eval_init_body(a, blockIdx.x - prefix[i]);
 }
 
 // K depth of the Delta-initialisation contractions (Y rows and keys).

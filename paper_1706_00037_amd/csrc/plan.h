@@ -98,6 +98,6 @@ struct GenTables {
 
 // Generation-0 seeds and scalars of the instances in the init table.
 hipError_t ubqp_queue_seed_init(const GenTables &t, hipStream_t st);
-// All launches of one generation; phase events are recorded when pe != null
-// (UBQP_PHASES + 1 of them).
-hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t *pe);
+// All launches of one generation.  When pe != null, events pe[0..5] bound the five
+// sequential phases and ae[2c], ae[2c + 1] the ascent launch of chunk group c.
+hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t *pe, hipEvent_t *ae = nullptr);

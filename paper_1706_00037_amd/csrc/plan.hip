@@ -136,7 +136,7 @@ hipError_t ubqp_queue_seed_init(const GenTables &t, hipStream_t st)
     return ubqp_launch_seed_init_batch(st, t.init.d_args, t.init.d_pre, t.init.count(), t.init.total());
 }
 
-hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t *pe)
+hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t *pe, hipEvent_t *ae)
 {
     hipError_t e = hipSuccess;
 #define Q(expr)                                   \
@@ -156,11 +156,14 @@ hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t 
     if (t.has_dump) Q(ubqp_launch_dump_batch(st, t.sel_cand.d_args, t.sel_cand.d_pre, n, t.sel_cand.total()));
     Q(ubqp_launch_screen_batch(st, t.scr.d_args, t.scr.d_pre, n, t.scr.total()));
     MARK(3);
-    for (const Chunk &ch : t.chunks) {
+    for (size_t c = 0; c < t.chunks.size(); c++) {
+        const Chunk &ch = t.chunks[c];
         Q(ubqp_launch_eval_batch(st, ch.planes == 1 ? UBQP_EPI_KEYS : UBQP_EPI_Y, ch.yr.d_args, ch.yr.d_pre,
                                  ch.yr.count(), ch.yr.total()));
+        if (ae) Q(hipEventRecord(ae[2 * c], st));
         Q(ubqp_launch_ascent_batch(st, ch.planes, ch.nb, ch.asc.d_args, ch.asc.d_pre, ch.asc.count(),
                                    ch.asc.total()));
+        if (ae) Q(hipEventRecord(ae[2 * c + 1], st));
     }
     MARK(4);
     Q(ubqp_launch_select_batch(st, t.sel_cand.d_args, t.sel_cand.d_pre, t.sel_cand.total(), t.sel_seed.d_pre,
@@ -185,7 +188,8 @@ struct ubqp_plan {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev0 = nullptr;
     std::vector<hipEvent_t> gen_ev; // end of each generation
-    std::vector<hipEvent_t> phase;  // UBQP_TIMING: G x (UBQP_PHASES + 1)
+    std::vector<hipEvent_t> phase;  // UBQP_TIMING: G x (UBQP_PHASE_ASCENT_KERNEL + 1)
+    std::vector<hipEvent_t> asc_ev; // UBQP_TIMING: G x chunk groups x 2
 };
 
 namespace {
@@ -201,6 +205,8 @@ void plan_free(ubqp_plan *pl)
     for (hipEvent_t e : pl->gen_ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : pl->phase)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : pl->asc_ev)
         if (e) (void)hipEventDestroy(e);
     if (pl->ev0) (void)hipEventDestroy(pl->ev0);
     if (pl->state) (void)hipFree(pl->state);
@@ -254,8 +260,12 @@ int plan_create(ubqp_ctx *ctx, int count, const ubqp_problem *const *probs, cons
     if (e == hipSuccess) e = hipEventCreate(&pl->ev0);
     pl->gen_ev.assign((size_t)pl->G, nullptr);
     for (size_t k = 0; e == hipSuccess && k < pl->gen_ev.size(); k++) e = hipEventCreate(&pl->gen_ev[k]);
-    if (pl->timing) pl->phase.assign((size_t)pl->G * (UBQP_PHASES + 1), nullptr);
+    if (pl->timing) {
+        pl->phase.assign((size_t)pl->G * (UBQP_PHASE_ASCENT_KERNEL + 1), nullptr);
+        pl->asc_ev.assign((size_t)pl->G * pl->t.chunks.size() * 2, nullptr);
+    }
     for (size_t k = 0; e == hipSuccess && k < pl->phase.size(); k++) e = hipEventCreate(&pl->phase[k]);
+    for (size_t k = 0; e == hipSuccess && k < pl->asc_ev.size(); k++) e = hipEventCreate(&pl->asc_ev[k]);
     if (e != hipSuccess) {
         plan_free(pl);
         return ubqp_hip_fail(ctx, e, "plan setup");
@@ -295,8 +305,11 @@ int plan_step(ubqp_plan *pl, int32_t generations)
         if (pl->exec) {
             UBQP_HIP_TRY(ctx, hipGraphLaunch(pl->exec, st));
         } else {
-            hipEvent_t *pe = pl->timing ? &pl->phase[(size_t)pl->g * (UBQP_PHASES + 1)] : nullptr;
-            UBQP_HIP_TRY(ctx, ubqp_queue_generation(pl->t, st, pe));
+            hipEvent_t *pe = pl->timing ? &pl->phase[(size_t)pl->g * (UBQP_PHASE_ASCENT_KERNEL + 1)] : nullptr;
+            hipEvent_t *ae = pl->timing && !pl->t.chunks.empty()
+                                 ? &pl->asc_ev[(size_t)pl->g * pl->t.chunks.size() * 2]
+                                 : nullptr;
+            UBQP_HIP_TRY(ctx, ubqp_queue_generation(pl->t, st, pe, ae));
         }
         UBQP_HIP_TRY(ctx, hipEventRecord(pl->gen_ev[(size_t)pl->g], st));
     }
@@ -327,13 +340,22 @@ int plan_result(ubqp_plan *pl, int i, ubqp_result *res)
             res->gen_ms_host[g] = ms;
         }
     if (res->phase_ms_host && !pl->phase.empty())
-        for (int32_t g = 0; g < pl->g; g++)
-            for (int k = 0; k < UBQP_PHASES; k++) {
+        for (int32_t g = 0; g < pl->g; g++) {
+            for (int k = 0; k < UBQP_PHASE_ASCENT_KERNEL; k++) {
                 float ms = 0.f;
-                const size_t b = (size_t)g * (UBQP_PHASES + 1);
+                const size_t b = (size_t)g * (UBQP_PHASE_ASCENT_KERNEL + 1);
                 UBQP_HIP_TRY(ctx, hipEventElapsedTime(&ms, pl->phase[b + k], pl->phase[b + k + 1]));
                 res->phase_ms_host[(size_t)g * UBQP_PHASES + k] = ms;
             }
+            double asc = 0.0;
+            const size_t nc = pl->t.chunks.size(), b = (size_t)g * nc * 2;
+            for (size_t c = 0; c < nc; c++) {
+                float ms = 0.f;
+                UBQP_HIP_TRY(ctx, hipEventElapsedTime(&ms, pl->asc_ev[b + 2 * c], pl->asc_ev[b + 2 * c + 1]));
+                asc += ms;
+            }
+            res->phase_ms_host[(size_t)g * UBQP_PHASES + UBQP_PHASE_ASCENT_KERNEL] = asc;
+        }
     res->have_best = hs.have_best;
     res->best_f = hs.have_best ? hs.best_f : INT64_MIN;
     res->generations = pl->g;

@@ -127,17 +127,20 @@ __global__ __launch_bounds__(THR) void screen_scatter(ScreenArgs a) { scatter_bo
 __global__ __launch_bounds__(THR) void screen_reduce_b(const ScreenArgs *args, const int64_t *prefix, int count)
 {
     const int i = ubqp_find_inst(prefix, count, blockIdx.x);
-    reduce_body(args[i], blockIdx.x - prefix[i]);
+    const ScreenArgs a = args[i];
+    reduce_body(a, blockIdx.x - prefix[i]);
 }
 __global__ __launch_bounds__(THR) void screen_count_b(const ScreenArgs *args, const int64_t *prefix, int count)
 {
     const int i = ubqp_find_inst(prefix, count, blockIdx.x);
-    count_body(args[i], blockIdx.x - prefix[i]);
+    const ScreenArgs a = args[i];
+    count_body(a, blockIdx.x - prefix[i]);
 }
 __global__ __launch_bounds__(THR) void screen_scatter_b(const ScreenArgs *args, const int64_t *prefix, int count)
 {
     const int i = ubqp_find_inst(prefix, count, blockIdx.x);
-    scatter_body(args[i], blockIdx.x - prefix[i]);
+    const ScreenArgs a = args[i];
+    scatter_body(a, blockIdx.x - prefix[i]);
 }
 
 }  // namespace

@@ -174,7 +174,8 @@ __global__ __launch_bounds__(THR) void seed_init_kernel(SelArgs a) { seed_init_b
     __global__ __launch_bounds__(THR) void NAME(const SelArgs *args, const int64_t *prefix, int count)  \
     {                                                                                                     \
         const int i = ubqp_find_inst(prefix, count, blockIdx.x);                                         \
-        BODY(args[i], blockIdx.x - prefix[i]);                                                            \
+        const SelArgs a = args[i];                                                                        \
+        BODY(a, blockIdx.x - prefix[i]);                                                                  \
     }
 BATCHED(seed_init_b, seed_init_body)
 BATCHED(dump_b, dump_body)
@@ -185,7 +186,8 @@ BATCHED(seed_fill_b, seed_fill_body)
 
 __global__ __launch_bounds__(THR) void incumbent_b(const SelArgs *args, int count)
 {
-    incumbent_body(args[blockIdx.x]);
+    const SelArgs a = args[blockIdx.x];
+    incumbent_body(a);
 }
 
 __global__ void advance_b(const SelArgs *args, int count)

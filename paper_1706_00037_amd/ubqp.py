@@ -22,7 +22,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "ubqp.h")
 UBQP_OK, UBQP_EINVAL, UBQP_ERANGE, UBQP_EASYM, UBQP_ENOMEM, UBQP_EDEVICE = 0, -1, -2, -3, -4, -5
 UBQP_DERIV_START, UBQP_TIMING, UBQP_NO_GRAPH, UBQP_AUTOTUNE = 1, 2, 4, 8
 UBQP_EVAL_VARIANTS = 6
-PHASES = ("diversify", "eval", "screen", "ascent", "select")
+PHASES = ("diversify", "eval", "screen", "ascent", "select", "ascent_kernel")  # the last is a part of "ascent"
 MAX_N, MAX_M, MAX_H = 8192, 1 << 22, 256
 INT64_MIN = -(1 << 63)
 
