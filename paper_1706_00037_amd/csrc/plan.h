@@ -68,8 +68,20 @@ template <typename A> struct Table {
 
 struct Chunk {
     int planes, nb;
+    int lane;  // side stream of its (planes, nb) group: chunks of one group stay in order
     Table<EvalArgs> yr;
     Table<AscArgs> asc;
+};
+
+// Side streams on which the (planes, NB) groups of the Delta initialisation and
+// ascent run concurrently (they touch different instances); the generation's
+// stream forks to them after the screen and joins them before the selection.
+#define UBQP_SIDE_STREAMS 3
+struct SideStreams {
+    hipStream_t s[UBQP_SIDE_STREAMS] = {};
+    hipEvent_t fork = nullptr, join[UBQP_SIDE_STREAMS] = {};
+    hipError_t create();
+    void destroy();
 };
 
 struct EvalGroup {         // instances whose row-dot contraction uses one variant
@@ -99,5 +111,8 @@ struct GenTables {
 // Generation-0 seeds and scalars of the instances in the init table.
 hipError_t ubqp_queue_seed_init(const GenTables &t, hipStream_t st);
 // All launches of one generation.  When pe != null, events pe[0..5] bound the five
-// sequential phases and ae[2c], ae[2c + 1] the ascent launch of chunk group c.
-hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t *pe, hipEvent_t *ae = nullptr);
+// sequential phases and ae[2c], ae[2c + 1] the ascent launch of chunk group c; the
+// groups then run in order on st.  Otherwise, with side != null and more than one
+// group, the groups run concurrently on the side streams.
+hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t *pe, hipEvent_t *ae = nullptr,
+                                 const SideStreams *side = nullptr);

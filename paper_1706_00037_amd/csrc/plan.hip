@@ -78,6 +78,7 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
         if (!join || (*join)[(size_t)(&r - inst.data())]) init.add(sl, ubqp_seed_blocks(sl));
         max_M = std::max(max_M, pr.M);
     }
+    std::map<std::pair<int, int>, int> group_lane;
     for (int64_t off = 0; off < max_M; off += UBQP_ASCENT_CHUNK) {
         std::map<std::pair<int, int>, Chunk> groups;
         for (const InstRef &r : inst) {
@@ -99,7 +100,19 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
             ch.yr.add(yr, ubqp_yrows_tiles(yr));
             ch.asc.add(as, ubqp_ascent_waves(as));
         }
-        for (auto &kv : groups) chunks.push_back(std::move(kv.second));
+        for (auto &kv : groups) {
+            // the same (planes, nb) group keeps its side stream across chunk offsets
+            int lane = 0;
+            auto it = group_lane.find(kv.first);
+            if (it != group_lane.end()) {
+                lane = it->second;
+            } else {
+                lane = (int)(group_lane.size() % UBQP_SIDE_STREAMS);
+                group_lane[kv.first] = lane;
+            }
+            kv.second.lane = lane;
+            chunks.push_back(std::move(kv.second));
+        }
     }
     host.clear();
     div.stage(host);
@@ -136,7 +149,31 @@ hipError_t ubqp_queue_seed_init(const GenTables &t, hipStream_t st)
     return ubqp_launch_seed_init_batch(st, t.init.d_args, t.init.d_pre, t.init.count(), t.init.total());
 }
 
-hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t *pe, hipEvent_t *ae)
+hipError_t SideStreams::create()
+{
+    hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    for (int i = 0; e == hipSuccess && i < UBQP_SIDE_STREAMS; i++) {
+        e = hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+    }
+    return e;
+}
+
+void SideStreams::destroy()
+{
+    for (int i = 0; i < UBQP_SIDE_STREAMS; i++) {
+        if (s[i]) (void)hipStreamSynchronize(s[i]);
+        if (s[i]) (void)hipStreamDestroy(s[i]);
+        if (join[i]) (void)hipEventDestroy(join[i]);
+        s[i] = nullptr;
+        join[i] = nullptr;
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    fork = nullptr;
+}
+
+hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t *pe, hipEvent_t *ae,
+                                 const SideStreams *side)
 {
     hipError_t e = hipSuccess;
 #define Q(expr)                                   \
@@ -156,14 +193,28 @@ hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t 
     if (t.has_dump) Q(ubqp_launch_dump_batch(st, t.sel_cand.d_args, t.sel_cand.d_pre, n, t.sel_cand.total()));
     Q(ubqp_launch_screen_batch(st, t.scr.d_args, t.scr.d_pre, n, t.scr.total()));
     MARK(3);
+    int lanes = 0;
+    for (const Chunk &ch : t.chunks) lanes = ch.lane + 1 > lanes ? ch.lane + 1 : lanes;
+    const bool fork = side && !pe && lanes > 1;
+    if (fork) {
+        Q(hipEventRecord(side->fork, st));
+        for (int l = 0; l < lanes; l++) Q(hipStreamWaitEvent(side->s[l], side->fork, 0));
+    }
     for (size_t c = 0; c < t.chunks.size(); c++) {
         const Chunk &ch = t.chunks[c];
-        Q(ubqp_launch_eval_batch(st, ch.planes == 1 ? UBQP_EPI_KEYS : UBQP_EPI_Y, ch.yr.d_args, ch.yr.d_pre,
+        hipStream_t cs = fork ? side->s[ch.lane] : st;
+        Q(ubqp_launch_eval_batch(cs, ch.planes == 1 ? UBQP_EPI_KEYS : UBQP_EPI_Y, ch.yr.d_args, ch.yr.d_pre,
                                  ch.yr.count(), ch.yr.total()));
-        if (ae) Q(hipEventRecord(ae[2 * c], st));
-        Q(ubqp_launch_ascent_batch(st, ch.planes, ch.nb, ch.asc.d_args, ch.asc.d_pre, ch.asc.count(),
+        if (ae) Q(hipEventRecord(ae[2 * c], cs));
+        Q(ubqp_launch_ascent_batch(cs, ch.planes, ch.nb, ch.asc.d_args, ch.asc.d_pre, ch.asc.count(),
                                    ch.asc.total()));
-        if (ae) Q(hipEventRecord(ae[2 * c + 1], st));
+        if (ae) Q(hipEventRecord(ae[2 * c + 1], cs));
+    }
+    if (fork) {
+        for (int l = 0; l < lanes; l++) {
+            Q(hipEventRecord(side->join[l], side->s[l]));
+            Q(hipStreamWaitEvent(st, side->join[l], 0));
+        }
     }
     MARK(4);
     Q(ubqp_launch_select_batch(st, t.sel_cand.d_args, t.sel_cand.d_pre, t.sel_cand.total(), t.sel_seed.d_pre,
@@ -184,6 +235,7 @@ struct ubqp_plan {
     GenTables t;
     bool timing = false, use_graph = true;
     hipStream_t cap_stream = nullptr;
+    SideStreams side;                // forked to by the (planes, NB) groups of a generation
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev0 = nullptr;
@@ -202,6 +254,7 @@ void plan_free(ubqp_plan *pl)
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    pl->side.destroy();
     for (hipEvent_t e : pl->gen_ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : pl->phase)
@@ -271,6 +324,11 @@ int plan_create(ubqp_ctx *ctx, int count, const ubqp_problem *const *probs, cons
         return ubqp_hip_fail(ctx, e, "plan setup");
     }
     pl->t.bind(pl->tables);
+    e = pl->side.create();
+    if (e != hipSuccess) {
+        plan_free(pl);
+        return ubqp_hip_fail(ctx, e, "side streams");
+    }
     // generation-0 seeds and scalars, then the start event
     e = ubqp_queue_seed_init(pl->t, ctx->stream);
     if (e == hipSuccess) e = hipEventRecord(pl->ev0, ctx->stream);
@@ -293,7 +351,7 @@ int plan_step(ubqp_plan *pl, int32_t generations)
         // capture one generation on a private stream (the caller's may be the null stream)
         UBQP_HIP_TRY(ctx, hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
         UBQP_HIP_TRY(ctx, hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-        const hipError_t qe = ubqp_queue_generation(pl->t, pl->cap_stream, nullptr);
+        const hipError_t qe = ubqp_queue_generation(pl->t, pl->cap_stream, nullptr, nullptr, &pl->side);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(pl->cap_stream, &g);
         if (qe != hipSuccess) return ubqp_hip_fail(ctx, qe, "generation capture");
@@ -309,7 +367,7 @@ int plan_step(ubqp_plan *pl, int32_t generations)
             hipEvent_t *ae = pl->timing && !pl->t.chunks.empty()
                                  ? &pl->asc_ev[(size_t)pl->g * pl->t.chunks.size() * 2]
                                  : nullptr;
-            UBQP_HIP_TRY(ctx, ubqp_queue_generation(pl->t, st, pe, ae));
+            UBQP_HIP_TRY(ctx, ubqp_queue_generation(pl->t, st, pe, ae, &pl->side));
         }
         UBQP_HIP_TRY(ctx, hipEventRecord(pl->gen_ev[(size_t)pl->g], st));
     }

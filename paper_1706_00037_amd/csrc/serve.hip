@@ -165,6 +165,7 @@ struct TableBuf {
 struct ubqp_server {
     ubqp_ctx *ctx = nullptr;
     hipStream_t cs = nullptr, up = nullptr;  // compute and upload streams, both the server's own
+    SideStreams side;                        // the generation's (planes, NB) groups fork to these
     char *pool_mem = nullptr;
     Pool pool;
     int max_active = 0;
@@ -428,7 +429,7 @@ hipError_t step(ubqp_server *s)
         s->spare_ev.push_back(s->inflight.front());
         s->inflight.pop_front();
     }
-    e = ubqp_queue_generation(s->tables, st, nullptr);
+    e = ubqp_queue_generation(s->tables, st, nullptr, nullptr, &s->side);
     hipEvent_t ev = nullptr;
     if (e == hipSuccess) e = take_event(s, &ev);
     if (e == hipSuccess) e = hipEventRecord(ev, st);
@@ -542,6 +543,7 @@ void server_free(ubqp_server *s)
     (void)hipSetDevice(s->ctx->device);
     if (s->cs) (void)hipStreamSynchronize(s->cs);
     if (s->up) (void)hipStreamSynchronize(s->up);
+    s->side.destroy();
     for (Slot &sl : s->slots) {
         if (sl.up_ev) (void)hipEventDestroy(sl.up_ev);
         if (sl.res_ev) (void)hipEventDestroy(sl.res_ev);
@@ -588,6 +590,7 @@ int ubqp_server_create(ubqp_ctx *ctx, int64_t pool_bytes, int32_t max_active, ub
     hipError_t e = hipMalloc(&s->pool_mem, pb);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->up, hipStreamNonBlocking);
+    if (e == hipSuccess) e = s->side.create();
     s->slots.resize((size_t)max_active);
     for (int i = 0; e == hipSuccess && i < max_active; i++) {
         e = hipEventCreateWithFlags(&s->slots[(size_t)i].up_ev, hipEventDisableTiming);
