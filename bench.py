@@ -42,7 +42,7 @@ PAPER_TABLE1_S = {2500: 0.7, 5000: 2.0, 6000: 3.0, 7000: 3.5}   # GPU seconds pe
 # counter passes summarised in profiles/counters_n7000_M16384.md (FETCH_SIZE and
 # WRITE_SIZE, calibrated against a 1 GiB device copy).  Valid for the kernels as
 # they were when the counters were taken; set to None when a kernel changes.
-TRAFFIC_GB = {"ascent": 8.81 + 0.004, "eval": 0.5617 + 0.0288}
+TRAFFIC_GB = {"ascent": None, "eval": 0.5617 + 0.0288}
 
 
 def log(msg):
@@ -218,9 +218,18 @@ def batched_bench(ctx, ubqp, torch, count=64, G=6, warm=2, seed=4):
     log(f"[batch] uploading {count} int16 instances")
     probs = [ctx.problem(make_wide_instance(torch, int(ns[k]), float(ds[k]), 4001 + k)) for k in range(count)]
     assert all(p.planes == 2 for p in probs)
-    params = [dict(M=4096, H=10, lam_num=1, lam_den=2, G=G, run_seed=4000 + k) for k in range(count)]
+    # tiles of the evaluation autotuned per (planes, n_pad, M) key when the batch is created
+    params = [dict(M=4096, H=10, lam_num=1, lam_den=2, G=G, run_seed=4000 + k, flags=ubqp.UBQP_AUTOTUNE)
+              for k in range(count)]
     ops = sum(2.0 * 4096 * int(n) * int(n) * 2 for n in ns)         # dense xQx work of one generation, 2 planes
+    t0 = time.perf_counter()
     b = ctx.batch(probs, params)
+    t_tune = time.perf_counter() - t0
+    chosen = {}
+    for p in probs:
+        v, _ = ctx.tune_eval(p, 4096)                                  # cached: the variant in use
+        chosen[str(v)] = chosen.get(str(v), 0) + 1
+    log(f"[batch] tuned eval variants (instances per variant): {chosen} in {t_tune:.2f} s")
     b.step(warm)
     b.result(0)
     torch.cuda.synchronize()
@@ -254,6 +263,7 @@ def batched_bench(ctx, ubqp, torch, count=64, G=6, warm=2, seed=4):
                 flips_per_generation=flips, ascent_row_gbs_if_all_time=row_bytes / t_batch / 1e9,
                 dense_tops=ops / t_batch / 1e12, sequential_ms_per_generation=t_seq * 1e3,
                 speedup_vs_sequential=t_seq / t_batch, timed_generations=G - warm,
+                eval_variants=chosen, tuning_s=t_tune,
                 workload="64 instances, n ~ U{1000..7000}, density in {0.1,0.5,1.0}, int16 coefficients "
                          "(hi/lo int8 planes), M=4096, H=10, lambda=1/2")
 

@@ -32,18 +32,46 @@
 namespace {
 
 
-// key += (q * s) * step, q = signed byte B of w, s = signed byte B of u, step
-// wave-uniform: one SDWA multiply (both bytes sign-extended) and one 24-bit mad.
-template <int B>
-__device__ inline int32_t update_key(int32_t key, uint32_t w, uint32_t u, int32_t step)
+typedef int32_t v16i __attribute__((ext_vector_type(16)));
+
+// Eight keys of one 16-column block (columns 8 h .. 8 h + 7): key += (q * s) * step
+// for q the signed bytes of q01 = {w0, w1} and s the signed bytes of the sign words
+// {u0, u1}.  One asm statement per eight columns, so no wait states are inserted
+// between the multiply-add pairs, and four products in flight.
+__device__ inline void update_keys8(int32_t &k0, int32_t &k1, int32_t &k2, int32_t &k3, int32_t &k4, int32_t &k5,
+                                    int32_t &k6, int32_t &k7, uint32_t w0, uint32_t w1, uint32_t u0, uint32_t u1,
+                                    int32_t step)
 {
-    int32_t prod;
-    asm("v_mul_i32_i24_sdwa %1, sext(%2), sext(%3) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_%5 "
-        "src1_sel:BYTE_%5\n\t"
-        "v_mad_i32_i24 %0, %1, %4, %0"
-        : "+v"(key), "=&v"(prod)
-        : "v"(w), "v"(u), "s"(step), "n"(B));
-    return key;
+    int32_t t0, t1, t2, t3;
+    asm("v_mul_i32_i24_sdwa %8, sext(%12), sext(%14) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:BYTE_0\n\t"
+        "v_mul_i32_i24_sdwa %9, sext(%12), sext(%14) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 src1_sel:BYTE_1\n\t"
+        "v_mul_i32_i24_sdwa %10, sext(%12), sext(%14) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_2 src1_sel:BYTE_2\n\t"
+        "v_mul_i32_i24_sdwa %11, sext(%12), sext(%14) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_3 src1_sel:BYTE_3\n\t"
+        "v_mad_i32_i24 %0, %8, %16, %0\n\t"
+        "v_mad_i32_i24 %1, %9, %16, %1\n\t"
+        "v_mad_i32_i24 %2, %10, %16, %2\n\t"
+        "v_mad_i32_i24 %3, %11, %16, %3\n\t"
+        "v_mul_i32_i24_sdwa %8, sext(%13), sext(%15) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:BYTE_0\n\t"
+        "v_mul_i32_i24_sdwa %9, sext(%13), sext(%15) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 src1_sel:BYTE_1\n\t"
+        "v_mul_i32_i24_sdwa %10, sext(%13), sext(%15) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_2 src1_sel:BYTE_2\n\t"
+        "v_mul_i32_i24_sdwa %11, sext(%13), sext(%15) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_3 src1_sel:BYTE_3\n\t"
+        "v_mad_i32_i24 %4, %8, %16, %4\n\t"
+        "v_mad_i32_i24 %5, %9, %16, %5\n\t"
+        "v_mad_i32_i24 %6, %10, %16, %6\n\t"
+        "v_mad_i32_i24 %7, %11, %16, %7"
+        : "+v"(k0), "+v"(k1), "+v"(k2), "+v"(k3), "+v"(k4), "+v"(k5), "+v"(k6), "+v"(k7), "=&v"(t0), "=&v"(t1),
+          "=&v"(t2), "=&v"(t3)
+        : "v"(w0), "v"(w1), "v"(u0), "v"(u1), "s"(step));
+}
+
+// Largest of 16 values: a balanced tree of three-input maxima.
+__device__ inline int32_t max16(const v16i &v)
+{
+    const int32_t a = max(max(v[0], v[1]), v[2]), b = max(max(v[3], v[4]), v[5]);
+    const int32_t c = max(max(v[6], v[7]), v[8]), d = max(max(v[9], v[10]), v[11]);
+    const int32_t e = max(max(v[12], v[13]), v[14]);
+    const int32_t ab = max(max(a, b), c), de = max(max(d, e), v[15]);
+    return max(ab, de);
 }
 
 // Largest value over the wave (DPP within rows of 16, then the four row leaders).
@@ -56,8 +84,6 @@ __device__ inline int32_t wave_max_i32(int32_t v)
     return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
                max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
-
-typedef int32_t v16i __attribute__((ext_vector_type(16)));
 
 // Column ownership of the int8 ascent: lane l owns [l PL, (l+1) PL), PL = 16 NB.
 // (Measured against lane l owning 1024 b + 16 l + t, which makes each 16-byte
@@ -110,11 +136,13 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
     const int32_t cap = a.max_flips > 0 ? a.max_flips : a.safety_cap;
     int32_t V;
     for (;;) {
-        int32_t best = INT32_MIN;
+        int32_t bmax[NB];
 #pragma unroll
-        for (int b = 0; b < NB; b++)
+        for (int b = 0; b < NB; b++) bmax[b] = max16(kk[b]);
+        int32_t best = bmax[0];
 #pragma unroll
-            for (int t = 0; t < 16; t += 2) best = max(best, max(kk[b][t], kk[b][t + 1]));
+        for (int b = 1; b + 1 < NB; b += 2) best = max(max(best, bmax[b]), bmax[b + 1]);
+        if ((NB & 1) == 0) best = max(best, bmax[NB - 1]);
         const int32_t ld = best >> 8;
         V = wave_max_i32(ld);
         if (V <= 0 || flips >= cap) break;
@@ -148,17 +176,14 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         for (int b = 0; b < NB; b++) w[b] = *(const uint4 *)(row + asc_col0<NB>(lane, b));
 #pragma unroll
         for (int b = 0; b < NB; b++) {
-            const uint32_t q4[4] = {w[b].x, w[b].y, w[b].z, w[b].w};
-            const uint32_t s4[4] = {ss[b][0], ss[b][1], ss[b][2], ss[b][3]};
+            int32_t k[16];
 #pragma unroll
-            for (int t = 0; t < 16; t++) {
-                switch (t & 3) {
-                case 0: kk[b][t] = update_key<0>(kk[b][t], q4[t >> 2], s4[t >> 2], step); break;
-                case 1: kk[b][t] = update_key<1>(kk[b][t], q4[t >> 2], s4[t >> 2], step); break;
-                case 2: kk[b][t] = update_key<2>(kk[b][t], q4[t >> 2], s4[t >> 2], step); break;
-                default: kk[b][t] = update_key<3>(kk[b][t], q4[t >> 2], s4[t >> 2], step); break;
-                }
-            }
+            for (int t = 0; t < 16; t++) k[t] = kk[b][t];
+            update_keys8(k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], w[b].x, w[b].y, ss[b][0], ss[b][1], step);
+            update_keys8(k[8], k[9], k[10], k[11], k[12], k[13], k[14], k[15], w[b].z, w[b].w, ss[b][2], ss[b][3],
+                         step);
+#pragma unroll
+            for (int t = 0; t < 16; t++) kk[b][t] = k[t];
         }
     }
     if (V > 0 && a.max_flips == 0 && lane == 0) atomicOr(a.err, 1);  // safety cap reached
@@ -177,26 +202,35 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
     }
 }
 
-// delta += (q * s) * step, q = signed word W of w, s = signed byte B of u.
-template <int Wd, int B>
-__device__ inline int32_t update_delta16(int32_t delta, uint32_t w, uint32_t u, int32_t step)
+// Eight deltas (columns 8 h .. 8 h + 7 of a 16-column block): delta += (q * s) * step
+// for q the signed words of {q0..q3} (two columns per word) and s the signed bytes
+// of {u0, u1}; one asm statement, four products in flight.
+__device__ inline void update_deltas8(int32_t &d0, int32_t &d1, int32_t &d2, int32_t &d3, int32_t &d4, int32_t &d5,
+                                      int32_t &d6, int32_t &d7, uint32_t q0, uint32_t q1, uint32_t q2, uint32_t q3,
+                                      uint32_t u0, uint32_t u1, int32_t step)
 {
-    int32_t prod;
-    asm("v_mul_i32_i24_sdwa %1, sext(%2), sext(%3) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_%5 "
-        "src1_sel:BYTE_%6\n\t"
-        "v_mad_i32_i24 %0, %1, %4, %0"
-        : "+v"(delta), "=&v"(prod)
-        : "v"(w), "v"(u), "s"(step), "n"(Wd), "n"(B));
-    return delta;
+    int32_t t0, t1, t2, t3;
+    asm("v_mul_i32_i24_sdwa %8, sext(%12), sext(%16) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:BYTE_0\n\t"
+        "v_mul_i32_i24_sdwa %9, sext(%12), sext(%16) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:BYTE_1\n\t"
+        "v_mul_i32_i24_sdwa %10, sext(%13), sext(%16) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:BYTE_2\n\t"
+        "v_mul_i32_i24_sdwa %11, sext(%13), sext(%16) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:BYTE_3\n\t"
+        "v_mad_i32_i24 %0, %8, %18, %0\n\t"
+        "v_mad_i32_i24 %1, %9, %18, %1\n\t"
+        "v_mad_i32_i24 %2, %10, %18, %2\n\t"
+        "v_mad_i32_i24 %3, %11, %18, %3\n\t"
+        "v_mul_i32_i24_sdwa %8, sext(%14), sext(%17) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:BYTE_0\n\t"
+        "v_mul_i32_i24_sdwa %9, sext(%14), sext(%17) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:BYTE_1\n\t"
+        "v_mul_i32_i24_sdwa %10, sext(%15), sext(%17) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:BYTE_2\n\t"
+        "v_mul_i32_i24_sdwa %11, sext(%15), sext(%17) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:BYTE_3\n\t"
+        "v_mad_i32_i24 %4, %8, %18, %4\n\t"
+        "v_mad_i32_i24 %5, %9, %18, %5\n\t"
+        "v_mad_i32_i24 %6, %10, %18, %6\n\t"
+        "v_mad_i32_i24 %7, %11, %18, %7"
+        : "+v"(d0), "+v"(d1), "+v"(d2), "+v"(d3), "+v"(d4), "+v"(d5), "+v"(d6), "+v"(d7), "=&v"(t0), "=&v"(t1),
+          "=&v"(t2), "=&v"(t3)
+        : "v"(q0), "v"(q1), "v"(q2), "v"(q3), "v"(u0), "v"(u1), "s"(step));
 }
 
-// Largest of 16 values.
-__device__ inline int32_t max16(const v16i &v)
-{
-    const int32_t a = max(max(v[0], v[1]), v[2]), b = max(max(v[3], v[4]), v[5]), c = max(max(v[6], v[7]), v[8]);
-    const int32_t d = max(max(v[9], v[10]), v[11]), e = max(max(v[12], v[13]), v[14]);
-    return max(max(max(a, b), max(c, d)), max(e, v[15]));
-}
 
 // int16 Q: |Delta| < 2^30, too wide to share 32 bits with a column index, so the
 // lane keeps Delta_i itself (and s_i as a byte) for its contiguous columns
@@ -318,22 +352,15 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
         }
 #pragma unroll
         for (int b = 0; b < NB; b++) {
-            const uint32_t q8[8] = {w[b][0].x, w[b][0].y, w[b][0].z, w[b][0].w,
-                                    w[b][1].x, w[b][1].y, w[b][1].z, w[b][1].w};
+            int32_t d[16];
 #pragma unroll
-            for (int t = 0; t < 16; t++) {
-                const uint32_t qw = q8[t >> 1], sw = ss[b][t >> 2];
-                switch (t & 7) {
-                case 0: dl[b][t] = update_delta16<0, 0>(dl[b][t], qw, sw, step); break;
-                case 1: dl[b][t] = update_delta16<1, 1>(dl[b][t], qw, sw, step); break;
-                case 2: dl[b][t] = update_delta16<0, 2>(dl[b][t], qw, sw, step); break;
-                case 3: dl[b][t] = update_delta16<1, 3>(dl[b][t], qw, sw, step); break;
-                case 4: dl[b][t] = update_delta16<0, 0>(dl[b][t], qw, sw, step); break;
-                case 5: dl[b][t] = update_delta16<1, 1>(dl[b][t], qw, sw, step); break;
-                case 6: dl[b][t] = update_delta16<0, 2>(dl[b][t], qw, sw, step); break;
-                default: dl[b][t] = update_delta16<1, 3>(dl[b][t], qw, sw, step); break;
-                }
-            }
+            for (int t = 0; t < 16; t++) d[t] = dl[b][t];
+            update_deltas8(d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], w[b][0].x, w[b][0].y, w[b][0].z,
+                           w[b][0].w, ss[b][0], ss[b][1], step);
+            update_deltas8(d[8], d[9], d[10], d[11], d[12], d[13], d[14], d[15], w[b][1].x, w[b][1].y, w[b][1].z,
+                           w[b][1].w, ss[b][2], ss[b][3], step);
+#pragma unroll
+            for (int t = 0; t < 16; t++) dl[b][t] = d[t];
         }
     }
     if (V > 0 && a.max_flips == 0 && lane == 0) atomicOr(a.err, 1);  // safety cap reached

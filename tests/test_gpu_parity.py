@@ -297,6 +297,37 @@ def test_multistart_matches_oracle(ctx, case):
         assert not r["have_best"]
 
 
+@pytest.mark.parametrize("cfg", ["cfg2", "cfg3"])
+def test_multistart_full_size_sampled(ctx, cfg):
+    """The bench's launch configuration at full size (n=2500, M=65536 and n=7000,
+    M=16384), two generations: generation-0 candidates rebuilt by the oracle one by
+    one and their objectives compared; every generation's screen statistics
+    recomputed by the oracle from the dumped objectives; the incumbent's value and
+    1-flip local optimality checked against the oracle."""
+    c = CONFIGS[cfg]
+    n, M, H, G = c["n"], c["M"], c["H"], 2
+    lam = tuple(c["lam"])
+    Q = make_instance(n, c["density"], c["lo"], c["hi"], c["inst_seed"])
+    prob = ctx.problem(Q)
+    dump = torch.zeros(G * M, dtype=torch.int64, device="cuda")
+    r = ctx.multistart(prob, M=M, H=H, lam_num=lam[0], lam_den=lam[1], G=G, run_seed=c["run_seed"], f_dump=dump)
+    fd = dump.cpu().numpy().reshape(G, M)
+    S = -(-M // (2 * H))
+    rng = np.random.default_rng(7)
+    cands = np.unique(np.concatenate([[0, 1, 2 * H - 1, 2 * H, M - 1], rng.choice(M, 20, replace=False)]))
+    for cnd in cands:
+        s = int(cnd) // (2 * H)
+        seed = oracle.random_solution(n, c["run_seed"], 0, S, s)
+        x = oracle.diversify(n, seed[None, :], H, 2 * H)[int(cnd) % (2 * H)]
+        assert oracle.f(Q, x) == fd[0, cnd], int(cnd)
+    for g in range(G):
+        idx, sm, mx = oracle.screen(fd[g], lam[0], lam[1])
+        assert (r["stats"][g, 0], r["stats"][g, 1], r["stats"][g, 2]) == (sm, mx, len(idx)), g
+        assert r["best_f"] >= mx
+    assert r["have_best"] and oracle.f(Q, r["best_x"]) == r["best_f"] == r["stats"][-1, 4]
+    assert (oracle.delta(Q, r["best_x"]) <= 0).all()
+
+
 def test_multistart_f_dump_matches_oracle(ctx):
     n, M, G = 120, 240, 3
     Q = make_instance(n, 0.4, -100, 100, 17)
