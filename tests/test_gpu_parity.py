@@ -423,6 +423,53 @@ def test_graph_replay_equals_direct_launches(ctx):
     assert np.array_equal(a["best_x"], b["best_x"])
 
 
+def test_graph_replays_with_eager_work_between(ctx):
+    """A captured generation replayed one step at a time, with eager library and
+    torch work and synchronisations between the replays: every replay's statistics
+    equal the directly launched run's (single instance, and a batch whose groups
+    fork onto side streams inside the graph)."""
+    from paper_1706_00037_amd import ubqp
+    G = 5
+    Q = make_instance(1200, 0.3, -100, 100, 91)
+    prob = ctx.problem(Q)
+    kw = dict(M=2500, H=10, lam_num=1, lam_den=2, G=G, run_seed=12)
+    ref = ctx.multistart(prob, flags=ubqp.UBQP_NO_GRAPH, **kw)
+    X = random_candidates(300, 1200, 92)
+    Xd = dev(X)
+    want = oracle.eval_many(Q, X, threads=8)
+    run = ctx.run(prob, **kw)
+    for g in range(G):
+        run.step(1)
+        r = run.result()
+        assert np.array_equal(r["stats"], ref["stats"][:g + 1]), g
+        fd = torch.zeros(300, dtype=torch.int64, device="cuda")
+        ctx.eval(prob, Xd, fd)                                    # eager work between replays
+        junk = torch.arange(1 << 20, device="cuda", dtype=torch.int64).sum()
+        torch.cuda.synchronize()
+        assert np.array_equal(fd.cpu().numpy(), want) and int(junk) == (1 << 20) * ((1 << 20) - 1) // 2
+    r = run.result()
+    run.close()
+    assert r["best_f"] == ref["best_f"] and np.array_equal(r["best_x"], ref["best_x"])
+
+    probs, params = [], []
+    for k, (n, d, lo, hi, M, H, lam, mf) in enumerate(_batch_cases()):
+        probs.append(ctx.problem(make_instance(n, d, lo, hi, 7100 + k)))
+        params.append(dict(M=M, H=H, lam_num=lam[0], lam_den=lam[1], G=3, max_flips=mf, run_seed=60 + k))
+    direct = [ctx.multistart(p, flags=ubqp.UBQP_NO_GRAPH, **pr) for p, pr in zip(probs, params)]
+    b = ctx.batch(probs, params)
+    for g in range(3):
+        b.step(1)
+        for k in range(len(probs)):
+            assert np.array_equal(b.result(k)["stats"], direct[k]["stats"][:g + 1]), (g, k)
+        junk = torch.ones(1 << 18, device="cuda").cumsum(0)[-1]
+        torch.cuda.synchronize()
+        assert float(junk) == float(1 << 18)
+    for k in range(len(probs)):
+        r = b.result(k)
+        assert r["best_f"] == direct[k]["best_f"] and np.array_equal(r["best_x"], direct[k]["best_x"]), k
+    b.close()
+
+
 def test_batch_rejects_unequal_generation_counts(ctx):
     from paper_1706_00037_amd import ubqp
     p1 = ctx.problem(make_instance(50, 0.5, -10, 10, 1))
