@@ -181,12 +181,31 @@ def serving_bench(ctx, ubqp, torch, R=300, warm=20, rate=200.0, distinct=32, max
                     max_running=st["max_running"], generations=st["generations"],
                     pool_high_gib=st["pool_high"] / 2**30, max_active=active)
 
+    def run_burst(active, count=120):
+        """Capacity: `count` requests submitted at once; solves/s over the drain."""
+        srv = ctx.server(pool_bytes=pool_gib << 30, max_active=active)
+        try:
+            t0 = time.monotonic_ns()
+            ids = [srv.submit(inst[r % distinct], **pr(2 * 10**6 + r)) for r in range(count)]
+            done = {}
+            while len(done) < count:
+                for x in srv.wait(timeout_s=5.0):
+                    done[x["id"]] = x
+        finally:
+            srv.close()
+        end = max(x["t_done_ns"] for x in done.values())
+        return count / ((end - t0) / 1e9)
+
     log(f"[serve] trace: {R} requests at {rate}/s, continuous batching (max_active={max_active})")
     batched = run_trace(max_active)
     log(f"[serve] batched: {batched}")
     log("[serve] same trace, one request at a time")
     plain = run_trace(1)
     log(f"[serve] one at a time: {plain}")
+    cap_b, cap_p = run_burst(max_active), run_burst(1)
+    log(f"[serve] capacity (120 requests at once): {cap_b:.1f} solves/s batched, {cap_p:.1f} one at a time")
+    batched["capacity_solves_per_s"] = cap_b
+    plain["capacity_solves_per_s"] = cap_p
     return dict(batched=batched, one_at_a_time=plain, requests=R, warmup_requests=warm, rate_per_s=rate,
                 distinct_instances=distinct,
                 workload=f"Poisson {rate:.0f} req/s; n ~ U{{500..7000}}, density ~ U[0.05,1], [-100,100], "
