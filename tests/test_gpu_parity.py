@@ -84,6 +84,8 @@ EVAL_CASES = [
     (129, 300, 0.5, -32768, 32767),
     (700, 513, 1.0, -32768, 32767),
     (1000, 300, 0.3, -300, 300),
+    (8192, 300, 0.3, -128, 127),          # the largest n, one plane
+    (8192, 130, 0.2, -32768, 32767),      # the largest n, two planes
 ]
 
 
@@ -204,6 +206,11 @@ ASCENT_CASES = [
     (1500, 16, 2, 0.5, -32768, 32767, 0),
     (2100, 8, 2, 0.3, -1000, 1000, 0),
     (600, 40, 3, 0.6, -4, 4, 0),          # many ties
+    (4500, 6, 2, 0.3, -32768, 32767, 0),  # two planes, 5 blocks of 16 columns per lane
+    (6000, 4, 2, 0.2, -32768, 32767, 0),
+    (7000, 4, 2, 0.5, -32768, 32767, 0),
+    (8192, 3, 1, 0.2, -32768, 32767, 0),  # the largest n
+    (5000, 40, 4, 0.05, -3, 3, 0),        # sparse, small values: long ascents with ties
 ]
 
 
@@ -287,6 +294,7 @@ def test_multistart_config1_full(ctx):
     dict(n=150, d=0.5, lo=-100, hi=100, M=200, H=10, lam=(1, 2), G=3, mf=3, flags=0),
     dict(n=90, d=0.5, lo=-100, hi=100, M=100, H=5, lam=(1, 1), G=2, mf=0, flags=0),   # nobody passes
     dict(n=1100, d=0.3, lo=-100, hi=100, M=2000, H=10, lam=(1, 2), G=3, mf=0, flags=0),
+    dict(n=4500, d=0.3, lo=-32768, hi=32767, M=300, H=10, lam=(1, 2), G=2, mf=0, flags=0),
 ])
 def test_multistart_matches_oracle(ctx, case):
     c = case
@@ -421,6 +429,31 @@ def test_graph_replay_equals_direct_launches(ctx):
     b = ctx.multistart(prob, flags=ubqp.UBQP_NO_GRAPH, **kw)
     assert np.array_equal(a["stats"], b["stats"]) and a["best_f"] == b["best_f"]
     assert np.array_equal(a["best_x"], b["best_x"])
+
+
+def test_batched_config4_shape(ctx):
+    """Instances shaped like the batched workload (int16 coefficients over the whole
+    range, n from 1000 to 7000, densities 0.1 / 0.5 / 1.0, 4096 candidates each,
+    autotuned evaluation): every incumbent is its own objective value and a 1-flip
+    local optimum; two instances give what they give alone."""
+    from paper_1706_00037_amd import ubqp
+    rng = np.random.default_rng(44)
+    ns = [1000, 7000] + list(rng.integers(1000, 7001, size=6))
+    ds = [0.1, 0.5, 1.0]
+    Qs = [make_instance(int(n), ds[k % 3], -32768, 32767, 4100 + k) for k, n in enumerate(ns)]
+    probs = [ctx.problem(Q) for Q in Qs]
+    assert all(p.planes == 2 for p in probs)
+    params = [dict(M=4096, H=10, lam_num=1, lam_den=2, G=2, run_seed=4000 + k, flags=ubqp.UBQP_AUTOTUNE)
+              for k in range(len(ns))]
+    res = ctx.multistart_batched(probs, params)
+    for k, (Q, r) in enumerate(zip(Qs, res)):
+        assert r["have_best"] and r["generations"] == 2, k
+        assert oracle.f(Q, r["best_x"]) == r["best_f"] == r["stats"][-1, 4], k
+        assert (oracle.delta(Q, r["best_x"]) <= 0).all(), k
+    for k in (0, 1):
+        alone = ctx.multistart(probs[k], **params[k])
+        assert alone["best_f"] == res[k]["best_f"] and np.array_equal(alone["stats"], res[k]["stats"]), k
+        assert np.array_equal(alone["best_x"], res[k]["best_x"]), k
 
 
 def test_graph_replays_with_eager_work_between(ctx):

@@ -132,6 +132,26 @@ def test_mix_matches_oracle(ctx, ub):
         _same(got[i], o, i)
 
 
+def test_full_size_requests_mix_equals_alone(ctx, ub):
+    """Requests of the serving workload's largest shapes (n up to 7000, 4096
+    candidates) overlapping on the device give what they give alone."""
+    cases = []
+    for k, (n, d) in enumerate([(7000, 0.5), (5000, 0.05), (3000, 1.0), (6500, 0.3)]):
+        Q = make_instance(n, d, -100, 100, 9500 + k).astype(np.int8)
+        cases.append((Q, dict(M=4096, H=10, lam_num=1, lam_den=2, G=2, run_seed=900 + k)))
+    alone = [_alone(ctx, Q, pr) for Q, pr in cases]
+    srv = ub.Server(ctx, pool_bytes=4 << 30, max_active=4)
+    try:
+        ids = [srv.submit(Q, **pr) for Q, pr in cases]
+        got = _collect(srv, ids)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["max_running"] >= 2
+    for k, i in enumerate(ids):
+        _same(got[i], alone[k], k)
+
+
 def test_admission_by_footprint_and_slots(ctx, ub):
     """Equal requests and a pool that holds two of them: never more than two run.
     Mixed requests in a small pool: the pool bound holds.  max_active = 1 runs one
