@@ -19,7 +19,9 @@ InstLayout ubqp_inst_layout(const ubqp_problem *p, const ubqp_params *pr)
     InstLayout L{};
     const int64_t M = pr->M, W = p->W;
     L.S = (M + 2 * pr->H - 1) / (2 * pr->H);
-    L.cap = M < UBQP_ASCENT_CHUNK ? M : UBQP_ASCENT_CHUNK;
+    const int64_t row_bytes = (int64_t)p->planes * p->n_pad * 4;
+    const int64_t fit = UBQP_DELTA_WS_BYTES / row_bytes / 256 * 256;
+    L.cap = M <= fit ? M : (fit > 256 ? fit : 256);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += ubqp_align256(bytes); return o; };
     L.seeds = take((size_t)(L.S * W * 8));
@@ -41,7 +43,6 @@ InstLayout ubqp_inst_layout(const ubqp_problem *p, const ubqp_params *pr)
 void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> *join)
 {
     count = (int)inst.size();
-    int64_t max_M = 0;
     for (const InstRef &r : inst) {
         const ubqp_problem *p = r.p;
         const ubqp_params &pr = r.pr;
@@ -76,16 +77,18 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
         sel_cand.add(sl, ubqp_cand_blocks(sl));
         sel_seed.add(sl, ubqp_seed_blocks(sl));
         if (!join || (*join)[(size_t)(&r - inst.data())]) init.add(sl, ubqp_seed_blocks(sl));
-        max_M = std::max(max_M, pr.M);
     }
     std::map<std::pair<int, int>, int> group_lane;
-    for (int64_t off = 0; off < max_M; off += UBQP_ASCENT_CHUNK) {
+    int64_t max_chunks = 0;
+    for (const InstRef &r : inst) max_chunks = std::max(max_chunks, (r.pr.M + r.L.cap - 1) / r.L.cap);
+    for (int64_t j = 0; j < max_chunks; j++) {
         std::map<std::pair<int, int>, Chunk> groups;
         for (const InstRef &r : inst) {
             const ubqp_problem *p = r.p;
             const ubqp_params &pr = r.pr;
-            if (pr.M <= off) continue;
             const InstLayout &L = r.L;
+            const int64_t off = j * L.cap;
+            if (pr.M <= off) continue;
             const int64_t cap = std::min<int64_t>(pr.M - off, L.cap);
             uint64_t *X = r.at<uint64_t>(L.X);
             int32_t *idx = r.at<int32_t>(L.idx), *Y = r.at<int32_t>(L.Y);

@@ -138,17 +138,17 @@ __device__ void rank_body(const SelArgs &a, int64_t bid)
     if (p < P && r) atomicAdd(&a.rank[p], r);
 }
 
-// The top S-1 passers become seeds 1..S-1.
+// The top S-1 passers become seeds 1..S-1: the instance's blocks stride over the
+// (passer, word) pairs, so consecutive threads copy consecutive words of a row.
 __device__ void place_body(const SelArgs &a, int64_t bid)
 {
     const int64_t P = a.scal->npass;
-    const int64_t p = bid * THR + threadIdx.x;
-    if (p >= P) return;
-    const int64_t r = a.rank[p];
-    if (r < a.S - 1) {
-        const uint64_t *src = a.X + (int64_t)a.idx[p] * a.W;
-        uint64_t *dst = a.seeds + (1 + r) * a.W;
-        for (int w = 0; w < a.W; w++) dst[w] = src[w];
+    const int64_t nblk = (a.M + THR - 1) / THR;
+    const int64_t total = P * a.W;
+    for (int64_t k = bid * THR + threadIdx.x; k < total; k += nblk * THR) {
+        const int64_t p = k / a.W, w = k - p * a.W;
+        const int64_t r = a.rank[p];
+        if (r < a.S - 1) a.seeds[(1 + r) * a.W + w] = a.X[(int64_t)a.idx[p] * a.W + w];
     }
 }
 

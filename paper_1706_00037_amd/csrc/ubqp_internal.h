@@ -11,8 +11,12 @@
 // Tile geometry of the int8 matrix-core contraction Y = X Q (eval_mfma.hip).
 #define UBQP_NPAD_ALIGN 128
 
-// Passers are ascended in chunks of at most this many (bounds the Y workspace).
+// The step-level ubqp_ascent works through passers in chunks of at most this many.
 #define UBQP_ASCENT_CHUNK 4096
+// A multi-start instance's Delta workspace holds at most this many bytes: its
+// passers are ascended in one chunk when planes * M * n_pad * 4 bytes fit, else in
+// chunks of as many passers as fit (a multiple of 256).
+#define UBQP_DELTA_WS_BYTES (1ll << 30)
 
 struct ubqp_ctx {
     int device = 0;

@@ -336,6 +336,25 @@ def test_multistart_full_size_sampled(ctx, cfg):
     assert (oracle.delta(Q, r["best_x"]) <= 0).all()
 
 
+def test_multistart_multi_chunk(ctx):
+    """More passers than one Delta workspace holds (n=8192: 32768 rows per GiB):
+    the passers are ascended in two chunks.  Screen statistics recomputed by the
+    oracle from the dumped objectives; every ascended passer is checked through the
+    incumbent and the flip count; the incumbent is a 1-flip local optimum."""
+    n, M = 8192, 70000
+    Q = make_instance(n, 0.05, -100, 100, 818)
+    prob = ctx.problem(Q)
+    dump = torch.zeros(M, dtype=torch.int64, device="cuda")
+    r = ctx.multistart(prob, M=M, H=10, lam_num=0, lam_den=1, G=1, run_seed=5, f_dump=dump)
+    fd = dump.cpu().numpy()
+    idx, sm, mx = oracle.screen(fd, 0, 1)
+    assert len(idx) > 32768                               # the second chunk holds passers
+    assert (r["stats"][0, 0], r["stats"][0, 1], r["stats"][0, 2]) == (sm, mx, len(idx))
+    assert r["have_best"] and r["best_f"] >= mx and r["stats"][0, 3] > 0
+    assert oracle.f(Q, r["best_x"]) == r["best_f"]
+    assert (oracle.delta(Q, r["best_x"]) <= 0).all()
+
+
 def test_multistart_f_dump_matches_oracle(ctx):
     n, M, G = 120, 240, 3
     Q = make_instance(n, 0.4, -100, 100, 17)
