@@ -306,7 +306,8 @@ UBQP_API int ubqp_server_wait(ubqp_server *server, int64_t timeout_us, ubqp_requ
  * running in one generation, pool high-water bytes, requests waiting, requests
  * admitted}. */
 UBQP_API int ubqp_server_stats(ubqp_server *server, int64_t out[8]);
-/* Message of the last server-level failure (never NULL). */
+/* Message of the last server-level failure (never NULL; valid until the next
+ * failing call on the server). */
 UBQP_API const char *ubqp_server_error(ubqp_server *server);
 UBQP_API int ubqp_server_destroy(ubqp_server *server);
 
