@@ -34,6 +34,8 @@ namespace {
 
 typedef int32_t v16i __attribute__((ext_vector_type(16)));
 
+
+
 // Eight keys of one 16-column block (columns 8 h .. 8 h + 7): key += (q * s) * step
 // for q the signed bytes of q01 = {w0, w1} and s the signed bytes of the sign words
 // {u0, u1}.  One asm statement per eight columns, so no wait states are inserted
@@ -116,7 +118,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
 #pragma unroll
         for (int t4 = 0; t4 < 4; t4++) {
             int4 v = {0, 0, 0, 0};
-            if (in) v = *(const int4 *)(yrow + 4 * t4);
+            if (in) v = ubqp_ldg16i(yrow + 4 * t4);
             const int32_t kv[4] = {v.x, v.y, v.z, v.w};
             uint32_t sw = 0;
 #pragma unroll
@@ -173,7 +175,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         const int8_t *row = qa + (int64_t)K * a.ncol_a;
         uint4 w[NB];
 #pragma unroll
-        for (int b = 0; b < NB; b++) w[b] = *(const uint4 *)(row + asc_col0<NB>(lane, b));
+        for (int b = 0; b < NB; b++) w[b] = ubqp_ldg16(row + asc_col0<NB>(lane, b));
 #pragma unroll
         for (int b = 0; b < NB; b++) {
             int32_t k[16];
@@ -269,9 +271,9 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
         for (int t4 = 0; t4 < 4; t4++) {
             int4 v0 = {0, 0, 0, 0}, v1 = {0, 0, 0, 0}, dg = {0, 0, 0, 0};
             if (in) {
-                v0 = *(const int4 *)(a.Y + p * a.n_pad + col0 + 4 * t4);
-                v1 = *(const int4 *)(a.Y + ystride + p * a.n_pad + col0 + 4 * t4);
-                dg = *(const int4 *)(a.diag + col0 + 4 * t4);
+                v0 = ubqp_ldg16i(a.Y + p * a.n_pad + col0 + 4 * t4);
+                v1 = ubqp_ldg16i(a.Y + ystride + p * a.n_pad + col0 + 4 * t4);
+                dg = ubqp_ldg16i(a.diag + col0 + 4 * t4);
             }
             const int32_t y0[4] = {v0.x, v0.y, v0.z, v0.w}, y1[4] = {v1.x, v1.y, v1.z, v1.w};
             const int32_t d[4] = {dg.x, dg.y, dg.z, dg.w};
@@ -347,8 +349,8 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
         uint4 w[NB][2];
 #pragma unroll
         for (int b = 0; b < NB; b++) {
-            w[b][0] = *(const uint4 *)(row + 16 * b);
-            w[b][1] = *(const uint4 *)(row + 16 * b + 8);
+            w[b][0] = ubqp_ldg16(row + 16 * b);
+            w[b][1] = ubqp_ldg16(row + 16 * b + 8);
         }
 #pragma unroll
         for (int b = 0; b < NB; b++) {

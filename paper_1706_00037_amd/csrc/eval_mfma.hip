@@ -140,11 +140,11 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     do {                                                                                      \
         _Pragma("unroll") for (int w_ = 0; w_ < KC / 64; w_++) {                              \
             const int wi_ = (kc) * (KC / 64) + w_;                                            \
-            aw[w_] = (xrow && wi_ < a.W) ? xrow[wi_] : 0ull;                                  \
+            aw[w_] = (xrow && wi_ < a.W) ? ubqp_ldg8(xrow + wi_) : 0ull;                      \
         }                                                                                     \
         const bool kin_ = (kc) * KC + bc16 * 16 < a.n_pad;                                    \
         _Pragma("unroll") for (int i_ = 0; i_ < BCH; i_++) {                                  \
-            br[i_] = kin_ ? *(const uint4 *)(qsrc + (int64_t)(BROWS * i_) * a.n_pad + (kc) * KC) \
+            br[i_] = kin_ ? ubqp_ldg16(qsrc + (int64_t)(BROWS * i_) * a.n_pad + (kc) * KC)     \
                           : uint4{0u, 0u, 0u, 0u};                                            \
         }                                                                                     \
         if (TRI && (kc) * KC + KC > n0) {                                                     \
@@ -254,7 +254,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
 #pragma unroll
         for (int ni = 0; ni < FN; ni++) {
             const int col = n0 + ni * 32 + r32;
-            dq[ni] = qp[(int64_t)col * a.n_pad + col];
+            dq[ni] = ubqp_ldg1(qp + (int64_t)col * a.n_pad + col);
         }
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
@@ -263,8 +263,8 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
                 const int64_t row = m0 + wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
                 uint64_t xw0 = 0, xw1 = 0;
                 if (row < Mrows) {
-                    if (word0 < a.W) xw0 = a.X[row * a.W + word0];
-                    if (word0 + 1 < a.W) xw1 = a.X[row * a.W + word0 + 1];
+                    if (word0 < a.W) xw0 = ubqp_ldg8(a.X + row * a.W + word0);
+                    if (word0 + 1 < a.W) xw1 = ubqp_ldg8(a.X + row * a.W + word0 + 1);
                 }
                 int s = 0;
 #pragma unroll
@@ -275,8 +275,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
                 // |s| <= 4 (2 * 128 n + 128) < 2^24: the 32-lane sum stays inside int32
                 s = row16_sum(s);
                 s += __shfl_xor(s, 16);
-                if (r32 == 0 && row < Mrows && s != 0)
-                    atomicAdd((unsigned long long *)&a.f[row], (unsigned long long)(wgt * (int64_t)s));
+                if (r32 == 0 && row < Mrows && s != 0) ubqp_atomic_add_i64(&a.f[row], wgt * (int64_t)s);
             }
         }
     } else if constexpr (EPI == EPI_Y) {

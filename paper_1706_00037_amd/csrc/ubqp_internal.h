@@ -74,6 +74,29 @@ int ubqp_ws_ensure(ubqp_ctx *ctx, int slot, size_t bytes, void **out);
         if (r_ != UBQP_OK) return r_;  \
     } while (0)
 
+// Loads through global-address-space pointers: pointers read from argument tables
+// are generic, so plain dereferences become flat loads (slower to issue and also
+// counted by the LDS/scalar wait counter); these become global loads.
+typedef unsigned int ubqp_v4u __attribute__((ext_vector_type(4)));
+__device__ inline uint4 ubqp_ldg16(const void *p)
+{
+    const ubqp_v4u v = *(const __attribute__((address_space(1))) ubqp_v4u *)p;
+    return uint4{v.x, v.y, v.z, v.w};
+}
+__device__ inline int4 ubqp_ldg16i(const void *p)
+{
+    const ubqp_v4u v = *(const __attribute__((address_space(1))) ubqp_v4u *)p;
+    return int4{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+}
+__device__ inline uint64_t ubqp_ldg8(const uint64_t *p) { return *(const __attribute__((address_space(1))) uint64_t *)p; }
+__device__ inline int8_t ubqp_ldg1(const int8_t *p) { return *(const __attribute__((address_space(1))) int8_t *)p; }
+// Relaxed device-scope int64 add in global memory (a global atomic, not a flat one).
+__device__ inline void ubqp_atomic_add_i64(int64_t *p, int64_t v)
+{
+    __hip_atomic_fetch_add((unsigned long long __attribute__((address_space(1))) *)p, (unsigned long long)v,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Batched launches: a kernel covering several instances gets, per instance, its
 // argument struct and the number of blocks (or waves) it needs; block b of the
 // grid belongs to the instance i with prefix[i] <= b < prefix[i + 1].
