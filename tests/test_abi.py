@@ -51,3 +51,31 @@ def test_product_path_does_not_touch_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text and "ubqp_oracle" not in text, f
+
+
+def test_request_footprint_host_logic():
+    """ubqp_request_footprint is host arithmetic: invalid requests give -1; the
+    footprint grows with n and M, two planes (int16 / int32 coefficients) cost more
+    than one, and it covers the resident Q planes, the ascent matrix, the population
+    and the Delta workspace."""
+    if not os.path.exists(ubqp.LIB_PATH):
+        pytest.skip("libubqp.so not built")
+    fp = ubqp.request_footprint
+    base = dict(M=4096, H=10, lam_num=1, lam_den=2, G=10)
+    assert fp(0, 1, base) == -1 and fp(8193, 1, base) == -1 and fp(100, 3, base) == -1
+    assert fp(100, 1, dict(base, G=0)) == -1 and fp(100, 1, dict(base, M=0)) == -1
+    assert fp(100, 1, dict(base, lam_num=3, lam_den=2)) == -1
+    prev = 0
+    assert fp(129, 1, base) > fp(128, 1, base)                 # next padding step
+    for n in (1, 64, 65, 500, 1000, 4000, 7000, 8192):
+        f1, f2, f4 = fp(n, 1, base), fp(n, 2, base), fp(n, 4, base)
+        assert f1 >= prev and f2 > f1 and f4 >= f2       # equal within one 128-column padding
+        prev = f1
+        n_pad = -(-n // 128) * 128
+        ncol = -(-n_pad // 1024) * 1024
+        W = -(-n // 64)
+        need = n_pad * n_pad + n_pad * ncol + 4096 * W * 8 + 4096 * 8 + 4096 * n_pad * 4
+        assert f1 >= need, (n, f1, need)
+        assert f2 >= 2 * n_pad * n_pad + 2 * n_pad * ncol + 2 * 4096 * n_pad * 4
+    assert fp(2000, 1, dict(base, M=8192)) > fp(2000, 1, base)
+    assert fp(2000, 1, dict(base, G=100)) > fp(2000, 1, base)
