@@ -56,6 +56,7 @@ def lib():
             "orc_f": (i64, [i32, P, P]),
             "orc_eval": (None, [i32, P, P, i64, P, i32]),
             "orc_diversify": (None, [i32, P, i64, i32, P, i64]),
+            "orc_blend": (None, [i32, P, i64, i64, i64, u64, P]),
             "orc_screen": (i64, [P, i64, i32, i32, P, P, P]),
             "orc_delta_recompute": (None, [i32, P, P, P]),
             "orc_delta": (None, [i32, P, P, P]),
@@ -119,6 +120,14 @@ def diversify(n, seeds, H, M):
     return X
 
 
+def blend(n, seeds, M, g, run_seed):
+    """Blending diversification of generation g (pairs of seeds, SplitMix64 masks)."""
+    seeds = np.ascontiguousarray(seeds, np.uint64)
+    X = np.zeros((M, words(n)), np.uint64)
+    lib().orc_blend(n, _p(seeds), seeds.shape[0], M, g, run_seed, _p(X))
+    return X
+
+
 def screen(fv, lam_num, lam_den):
     fv = np.ascontiguousarray(fv, np.int64)
     M = fv.shape[0]
@@ -164,6 +173,9 @@ def derivative_start(Q):
     x = np.zeros(words(Q.shape[0]), np.uint64)
     lib().orc_derivative_start(Q.shape[0], _p(Q), _p(x))
     return x
+
+
+FLAG_DERIV_START, FLAG_BLEND = 1, 2
 
 
 def multistart(Q, M, H, lam_num, lam_den, G, max_flips=0, run_seed=0, flags=0, threads=1,

@@ -18,7 +18,8 @@
  *                    stop at a 1-flip local optimum or after max flips, no tabu
  *                    (Pseudocode section; Glover et al. 2002 for the deltas)
  *   diversification  Glover's generator: flip every h-th variable, plus the
- *                    complement (Pseudocode section, Glover 1998)
+ *                    complement (Pseudocode section, Glover 1998); or blending
+ *                    two seeds (Pseudocode section, rule read here)
  *   main loop        diversify -> evaluate -> screen -> ascent -> update best
  *                    (Fig. 2)
  * The readings taken where the paper is silent are listed at each function.
@@ -124,6 +125,39 @@ ORC_API void orc_diversify(int32_t n, const uint64_t *seeds, int64_t S, int32_t 
             if (j % h == 0) b ^= 1;
             if (comp) b ^= 1;
             put_bit(x, j, b);
+        }
+    }
+}
+
+/*
+ * Blending (breeding) diversification.  The paper reports diversification by
+ * blending two solutions into new ones (Pseudocode section) without a rule;
+ * the reading taken here is a uniform crossover of two seeds with a random mask:
+ *   candidates come in pairs k = c / 2 (k < ceil(M / 2));
+ *   parents are seeds a = k mod S and b = (a + 1 + k / S + g) mod S;
+ *   mask word w is output 2^62 + (g * ceil(M / 2) + k) * W + w of SplitMix64
+ *   seeded with run_seed (a counter range apart from the random solutions');
+ *   bit j of the child is the parent-a bit where the mask is 1 and the parent-b
+ *   bit where it is 0 for even c, the other way round for odd c.
+ * Positions >= n are 0 (the seeds' are).
+ */
+ORC_API void orc_blend(int32_t n, const uint64_t *seeds, int64_t S, int64_t M, int64_t g, uint64_t run_seed,
+                       uint64_t *X)
+{
+    int64_t W = words_for(n);
+    int64_t pairs = (M + 1) / 2;
+    for (int64_t c = 0; c < M; c++) {
+        int64_t k = c / 2;
+        int64_t a = k % S;
+        int64_t b = (a + 1 + k / S + g) % S;
+        int odd = (int)(c % 2);
+        uint64_t *x = X + c * W;
+        memset(x, 0, (size_t)W * 8);
+        for (int64_t j = 0; j < n; j++) {
+            uint64_t mw = orc_splitmix64(run_seed, (1ull << 62) + (uint64_t)((g * pairs + k) * W + j / 64));
+            int m = (int)((mw >> (j % 64)) & 1u);
+            int from_a = odd ? !m : m;
+            put_bit(x, j, get_bit(seeds + (from_a ? a : b) * W, j));
         }
     }
 }
@@ -257,7 +291,8 @@ typedef struct {
     int32_t lam_den;
     int32_t G;          /* generations                                         */
     int32_t max_flips;  /* 0 = ascend to a 1-flip local optimum                */
-    int32_t flags;      /* bit 0: generation-0 seed 0 is the derivative start  */
+    int32_t flags;      /* bit 0: generation-0 seed 0 is the derivative start; */
+                        /* bit 1: blending diversification instead of Glover's  */
     uint64_t run_seed;
 } orc_params;
 
@@ -271,7 +306,8 @@ static int rank_cmp(const void *a, const void *b)
 
 /*
  * The multi-start loop of Fig. 2, one generation at a time with M candidates:
- *   1. candidates: Glover diversification of the S = ceil(M / 2H) seeds;
+ *   1. candidates: Glover diversification of the S = ceil(M / 2H) seeds
+ *      (or blending of pairs of them, flags & 2);
  *   2. evaluate f for every candidate;
  *   3. screen with T(lambda) over this generation's Sum and Max;
  *   4. steepest ascent of every passer;
@@ -316,7 +352,8 @@ ORC_API int32_t orc_multistart(int32_t n, const int32_t *Q, const orc_params *pr
 
     for (int64_t g = 0; g < pr->G; g++) {
         if (dump && dump->seeds) memcpy(dump->seeds + g * S * W, seeds, (size_t)(S * W) * 8);
-        orc_diversify(n, seeds, S, (int32_t)H, X, M);
+        if (pr->flags & 2) orc_blend(n, seeds, S, M, g, pr->run_seed, X);
+        else orc_diversify(n, seeds, S, (int32_t)H, X, M);
         orc_eval(n, Q, X, M, f, threads);
         if (dump && dump->f) memcpy(dump->f + g * M, f, (size_t)M * 8);
         int64_t sum, mx;
