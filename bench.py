@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-lam-sweep", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-blend", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-active", type=int, default=32)
@@ -361,6 +362,27 @@ def main():
             log(f"[bench] lambda {ln}/{ld}: {tl:.3f} ms/generation, P={stl[:, 2].mean():.0f} "
                 f"flips={stl[:, 3].mean():.0f}")
 
+    # ---- the headline workload with blending diversification -------------------------
+    blend = None
+    if not args.no_blend:
+        rb = ctx.run(prob, M=M, H=H, lam_num=lam_num, lam_den=lam_den, G=Wm + K, run_seed=c["run_seed"],
+                     flags=ubqp.UBQP_TIMING | ubqp.UBQP_BLEND)
+        rb.step(Wm)
+        rb.result()
+        tb0 = time.perf_counter()
+        rb.step(K)
+        rbr = rb.result()
+        tb = (time.perf_counter() - tb0) * 1e3 / K
+        rb.close()
+        stb = rbr["stats"][Wm:]
+        blend = dict(ms_per_generation=tb, evals_per_s=M / (tb * 1e-3),
+                     phases_ms={name: float(rbr["phase_ms"][Wm:, i].mean()) for i, name in enumerate(ubqp.PHASES)},
+                     passers_per_gen=float(stb[:, 2].mean()), flips_per_gen=float(stb[:, 3].mean()),
+                     best_f=int(rbr["best_f"]), best_f_glover=int(res["best_f"]), generations=Wm + K)
+        log(f"[bench] blending: {tb:.3f} ms/generation, diversify {blend['phases_ms']['diversify']:.4f} ms, "
+            f"P={stb[:, 2].mean():.0f} flips={stb[:, 3].mean():.0f}, best f {rbr['best_f']} "
+            f"(Glover {res['best_f']}) after {Wm + K} generations")
+
     # ---- evaluation alone (the batched exact objective) ------------------------
     X = random_candidates(M, n, 5)
     Xd = torch.from_numpy(X.view(np.int64)).cuda()
@@ -481,6 +503,7 @@ def main():
                       "traffic_gb_per_launch": TRAFFIC_GB["eval"]},
         "e1_replica": e1_rep,
         "lambda_sweep": lam_sweep,
+        "blend": blend,
         "batched": batched,
         "serving": serving,
     }

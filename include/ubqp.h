@@ -54,6 +54,7 @@ extern "C" {
 #define UBQP_TIMING 2u      /* record stream events around every phase of a generation */
 #define UBQP_NO_GRAPH 4u    /* launch every kernel directly instead of replaying a captured generation */
 #define UBQP_AUTOTUNE 8u    /* tune the evaluation's tiling for every instance first (ubqp_tune_eval) */
+#define UBQP_BLEND 16u      /* diversify by blending pairs of seeds (ubqp_blend) instead of Glover's generator */
 
 /* variants of the evaluation's matrix-core tiling (ubqp_tune_eval) */
 #define UBQP_EVAL_VARIANTS 6
@@ -80,7 +81,8 @@ typedef struct {
     int32_t lam_den;
     int32_t G;          /* generations (iterations of the main loop), >= 1             */
     int32_t max_flips;  /* flips per ascent, 0 = until a 1-flip local optimum          */
-    uint32_t flags;     /* UBQP_DERIV_START | UBQP_TIMING | UBQP_NO_GRAPH | UBQP_AUTOTUNE */
+    uint32_t flags;     /* UBQP_DERIV_START | UBQP_TIMING | UBQP_NO_GRAPH | UBQP_AUTOTUNE |   */
+                        /* UBQP_BLEND; other bits are rejected (UBQP_EINVAL)             */
     uint64_t run_seed;  /* SplitMix64 seed of the random solutions                     */
 } ubqp_params;
 
@@ -143,6 +145,21 @@ UBQP_API int ubqp_problem_info(const ubqp_problem *prob, int32_t *n, int32_t *n_
  */
 UBQP_API int ubqp_diversify(ubqp_ctx *ctx, int32_t n, const uint64_t *seeds_d, int64_t S, int32_t H,
                    uint64_t *X_d, int64_t M);
+
+/*
+ * Blending diversification (Pseudocode section: new solutions bred from two
+ * solutions; the paper gives no rule, this is a uniform crossover).  Candidates
+ * come in pairs k = c / 2 (0 <= c < M); pair k of generation g has parents
+ * a = k mod S and b = (a + 1 + k / S + g) mod S, and mask word w equal to
+ * output 2^62 + (g ceil(M/2) + k) W + w of SplitMix64 seeded with run_seed.
+ * Candidate 2k takes a's bits where the mask is 1 and b's where it is 0;
+ * candidate 2k + 1 takes the opposite choice.  seeds_d: S x W (bits >= n zero),
+ * X_d: M x W (output, bits >= n cleared).  Requires S >= 1 and 0 <= g < 2^31.
+ * Multi-start runs use it in place of ubqp_diversify under UBQP_BLEND, with
+ * g the generation index.
+ */
+UBQP_API int ubqp_blend(ubqp_ctx *ctx, int32_t n, const uint64_t *seeds_d, int64_t S, int64_t M, int64_t g,
+                        uint64_t run_seed, uint64_t *X_d);
 
 /*
  * Exact objective of M candidates (Introduction, problem (P); the evaluation
@@ -271,7 +288,7 @@ UBQP_API int ubqp_multistart_batched(ubqp_ctx *ctx, int32_t count, const ubqp_pr
  * 4 (int32 within [-32768, 32767], hi/lo planes).  q_host, best_x_host (W words)
  * and stats_host (G x 5, may be NULL) must stay valid until the request is
  * reported done; page-locked q_host makes the upload asynchronous.  params.flags
- * may hold UBQP_DERIV_START only.
+ * may hold UBQP_DERIV_START and UBQP_BLEND only.
  *
  * ubqp_server_wait blocks until at least one request has finished or timeout_us
  * (< 0: no limit) has passed, and moves up to `max` finished requests into

@@ -91,6 +91,8 @@ int ubqp_check_params(ubqp_ctx *ctx, const ubqp_problem *p, const ubqp_params *p
         return ubqp_fail(ctx, UBQP_EINVAL, "lambda=%d/%d outside [0, 1]", pr->lam_num, pr->lam_den);
     if (pr->G < 1) return ubqp_fail(ctx, UBQP_EINVAL, "G < 1");
     if (pr->max_flips < 0) return ubqp_fail(ctx, UBQP_EINVAL, "max_flips < 0");
+    const uint32_t known = UBQP_DERIV_START | UBQP_TIMING | UBQP_NO_GRAPH | UBQP_AUTOTUNE | UBQP_BLEND;
+    if (pr->flags & ~known) return ubqp_fail(ctx, UBQP_EINVAL, "unknown flags 0x%x", pr->flags & ~known);
     return UBQP_OK;
 }
 
@@ -164,6 +166,31 @@ int ubqp_diversify(ubqp_ctx *ctx, int32_t n, const uint64_t *seeds_d, int64_t S,
     a.H = H;
     a.X = X_d;
     a.total = M * a.W;
+    UBQP_HIP_TRY(ctx, ubqp_launch_diversify(ctx->stream, a));
+    return UBQP_OK;
+}
+
+int ubqp_blend(ubqp_ctx *ctx, int32_t n, const uint64_t *seeds_d, int64_t S, int64_t M, int64_t g,
+               uint64_t run_seed, uint64_t *X_d)
+{
+    if (!ctx || !seeds_d || !X_d) return ubqp_fail(ctx, UBQP_EINVAL, "null argument");
+    UBQP_TRY(check_words(ctx, n, M));
+    if (S < 1) return ubqp_fail(ctx, UBQP_EINVAL, "S < 1");
+    if (g < 0 || g > INT32_MAX) return ubqp_fail(ctx, UBQP_EINVAL, "g=%lld outside [0, 2^31)", (long long)g);
+    UBQP_TRY(ubqp_set_device(ctx));
+    DivArgs a{};
+    a.seeds = seeds_d;
+    a.n = n;
+    a.W = (n + 63) / 64;
+    a.H = 1;
+    a.X = X_d;
+    a.total = M * a.W;
+    a.blend = 1;
+    a.M = M;
+    a.S = S;
+    a.run_seed = run_seed;
+    a.scal = nullptr;
+    a.g = g;
     UBQP_HIP_TRY(ctx, ubqp_launch_diversify(ctx->stream, a));
     return UBQP_OK;
 }

@@ -58,6 +58,11 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
         d.H = pr.H;
         d.X = X;
         d.total = pr.M * p->W;
+        d.blend = (pr.flags & UBQP_BLEND) ? 1 : 0;
+        d.M = pr.M;
+        d.S = L.S;
+        d.run_seed = pr.run_seed;
+        d.scal = sc;
         div.add(d, ubqp_div_blocks(d));
         EvalArgs ea = ubqp_eval_args(p, X, pr.M, f);
         einit.add(ea, ubqp_eval_init_blocks(ea));

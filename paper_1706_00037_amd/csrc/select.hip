@@ -18,18 +18,10 @@ namespace {
 
 constexpr int THR = 256;
 
-__device__ inline uint64_t splitmix_output(uint64_t seed, uint64_t i)
-{
-    uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 __device__ inline uint64_t random_word(uint64_t run_seed, int64_t g, int64_t S, int64_t s, int32_t W, int32_t w,
                                        int32_t n)
 {
-    uint64_t v = splitmix_output(run_seed, (uint64_t)((g * S + s) * W + w));
+    uint64_t v = ubqp_splitmix64(run_seed, (uint64_t)((g * S + s) * W + w));
     const int32_t tail = n - 64 * w;
     if (tail < 64) v &= (1ull << tail) - 1ull;
     return v;

@@ -620,8 +620,8 @@ int ubqp_server_submit(ubqp_server *s, int32_t n, const void *q_host, int32_t el
         set_err(s, "null argument");
         return UBQP_EINVAL;
     }
-    if (params->flags & ~UBQP_DERIV_START) {
-        set_err(s, "request flags other than UBQP_DERIV_START");
+    if (params->flags & ~(UBQP_DERIV_START | UBQP_BLEND)) {
+        set_err(s, "request flags other than UBQP_DERIV_START and UBQP_BLEND");
         return UBQP_EINVAL;
     }
     Req *r = new (std::nothrow) Req();

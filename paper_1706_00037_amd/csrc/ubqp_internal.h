@@ -54,6 +54,16 @@ struct ubqp_scal {
     int32_t pad_;
 };
 
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter generator: output i of the
+// generator seeded with `seed`.
+__device__ inline uint64_t ubqp_splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 // ---- error handling shared by abi.hip and plan.hip ----------------------------
 int ubqp_fail(ubqp_ctx *ctx, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 int ubqp_hip_fail(ubqp_ctx *ctx, hipError_t e, const char *what);
@@ -138,11 +148,16 @@ int ubqp_check_verdict(ubqp_ctx *ctx, const ubqp_check_flags &fl, int32_t n);
 // Every kernel body takes one of these for its instance; single-instance
 // launches pass it by value, batched launches read it from a device array.
 
-struct DivArgs {             // Glover diversification
+struct DivArgs {             // Glover diversification, or blending of pairs of seeds
     const uint64_t *seeds;
     int32_t n, W, H;
     uint64_t *X;
     int64_t total;           // M * W output words
+    int32_t blend;           // 0: Glover's generator; 1: blending (the fields below)
+    int64_t M, S;
+    uint64_t run_seed;
+    const ubqp_scal *scal;   // generation index from scal->gen, or the constant g when null
+    int64_t g;
 };
 
 struct EvalArgs {            // int8 matrix-core contraction Y = X Q and its epilogues

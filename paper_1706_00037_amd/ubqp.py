@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libubqp.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ubqp.h")
 
 UBQP_OK, UBQP_EINVAL, UBQP_ERANGE, UBQP_EASYM, UBQP_ENOMEM, UBQP_EDEVICE = 0, -1, -2, -3, -4, -5
-UBQP_DERIV_START, UBQP_TIMING, UBQP_NO_GRAPH, UBQP_AUTOTUNE = 1, 2, 4, 8
+UBQP_DERIV_START, UBQP_TIMING, UBQP_NO_GRAPH, UBQP_AUTOTUNE, UBQP_BLEND = 1, 2, 4, 8, 16
 UBQP_EVAL_VARIANTS = 6
 PHASES = ("diversify", "eval", "screen", "ascent", "select", "ascent_kernel")  # the last is a part of "ascent"
 MAX_N, MAX_M, MAX_H = 8192, 1 << 22, 256
@@ -73,6 +73,7 @@ def load():
         "ubqp_problem_destroy": [P],
         "ubqp_problem_info": [P, P, P, P],
         "ubqp_diversify": [P, i32, P, i64, i32, P, i64],
+        "ubqp_blend": [P, i32, P, i64, i64, i64, u64, P],
         "ubqp_eval": [P, P, P, i64, P],
         "ubqp_eval_variant": [P, P, P, i64, P, i32],
         "ubqp_tune_eval": [P, P, i64, ctypes.POINTER(i32), P],
@@ -383,6 +384,14 @@ class Context:
         M = X.numel() // W if M is None else M
         self._call("ubqp_diversify", self.h, n, self._t(seeds, torch.int64, S * W, "seeds"), S, H,
                    self._t(X, torch.int64, M * W, "X"), M)
+
+    def blend(self, n, seeds, X, g, run_seed, M=None):
+        torch = self.torch
+        W = _words(n)
+        S = seeds.numel() // W
+        M = X.numel() // W if M is None else M
+        self._call("ubqp_blend", self.h, n, self._t(seeds, torch.int64, S * W, "seeds"), S, M, g, run_seed,
+                   self._t(X, torch.int64, M * W, "X"))
 
     def eval(self, prob: Problem, X, f, M=None):
         torch = self.torch
