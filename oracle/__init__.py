@@ -38,6 +38,18 @@ class Params(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("run_seed", ctypes.c_uint64)]
 
 
+class SeqParams(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("samples", ctypes.c_int64), ("H", ctypes.c_int64),
+                ("lam_num", ctypes.c_int32), ("lam_den", ctypes.c_int32), ("max_flips", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("run_seed", ctypes.c_uint64)]
+
+
+class SeqOut(ctypes.Structure):
+    _fields_ = [("best_f", ctypes.c_int64), ("have_best", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("sample_sum", ctypes.c_int64), ("start_f", ctypes.c_int64), ("passers", ctypes.c_int64),
+                ("flips", ctypes.c_int64), ("improvements", ctypes.c_int64)]
+
+
 class Dump(ctypes.Structure):
     _fields_ = [("f", ctypes.c_void_p), ("fa", ctypes.c_void_p), ("pass_", ctypes.c_void_p),
                 ("xa", ctypes.c_void_p), ("seeds", ctypes.c_void_p)]
@@ -57,6 +69,7 @@ def lib():
             "orc_eval": (None, [i32, P, P, i64, P, i32]),
             "orc_diversify": (None, [i32, P, i64, i32, P, i64]),
             "orc_blend": (None, [i32, P, i64, i64, i64, u64, P]),
+            "orc_sequential": (None, [i32, P, P, P, P, P, P, i64, i32]),
             "orc_screen": (i64, [P, i64, i32, i32, P, P, P]),
             "orc_delta_recompute": (None, [i32, P, P, P]),
             "orc_delta": (None, [i32, P, P, P]),
@@ -203,3 +216,23 @@ def multistart(Q, M, H, lam_num, lam_den, G, max_flips=0, run_seed=0, flags=0, t
     if dump:
         out.update(arrs)
     return out
+
+
+def sequential(Q, iterations, samples, H, lam_num, lam_den, max_flips=0, run_seed=0, threads=1,
+               history_cap=1 << 16):
+    """The main loop of Fig. 2 one candidate per iteration (orc_sequential).
+    Returns dict(best_f, best_x, have_best, sample_sum, start_f, passers, flips,
+    improvements, history[k, 2] = (iteration, value), f_dump[iterations])."""
+    Q = _q(Q)
+    n = Q.shape[0]
+    pr = SeqParams(iterations, samples, H, lam_num, lam_den, max_flips, 0, run_seed)
+    out = SeqOut()
+    bx = np.zeros(words(n), np.uint64)
+    fd = np.zeros(iterations, np.int64)
+    hist = np.zeros((history_cap, 2), np.int64)
+    lib().orc_sequential(n, _p(Q), ctypes.byref(pr), ctypes.byref(out), _p(bx), _p(fd), _p(hist), history_cap,
+                         threads)
+    k = min(out.improvements, history_cap)
+    return dict(best_f=out.best_f, best_x=bx, have_best=bool(out.have_best), sample_sum=out.sample_sum,
+                start_f=out.start_f, passers=out.passers, flips=out.flips, improvements=out.improvements,
+                history=hist[:k].copy(), f_dump=fd)

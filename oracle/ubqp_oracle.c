@@ -21,7 +21,8 @@
  *                    complement (Pseudocode section, Glover 1998); or blending
  *                    two seeds (Pseudocode section, rule read here)
  *   main loop        diversify -> evaluate -> screen -> ascent -> update best
- *                    (Fig. 2)
+ *                    (Fig. 2), a generation of many candidates at a time, or
+ *                    one candidate per iteration as printed (orc_sequential)
  * The readings taken where the paper is silent are listed at each function.
  *
  * Pins that do not come from this file are in tests/test_oracle_*.py.
@@ -395,4 +396,107 @@ ORC_API int32_t orc_multistart(int32_t n, const int32_t *Q, const orc_params *pr
     *best_f = bf;
     free(seeds); free(X); free(f); free(flips); free(idx); free(rk);
     return have_best;
+}
+
+/* -------------------------------------------------- sequential main loop */
+
+typedef struct {
+    int64_t iterations; /* I: iterations of the main loop                      */
+    int64_t samples;    /* random solutions whose mean objective is Mean       */
+    int64_t H;          /* cycle of the diversification step                   */
+    int32_t lam_num;    /* lambda = lam_num / lam_den                          */
+    int32_t lam_den;
+    int32_t max_flips;  /* 0 = ascend to a 1-flip local optimum                */
+    int32_t pad_;
+    uint64_t run_seed;
+} orc_seq_params;
+
+typedef struct {
+    int64_t best_f;
+    int32_t have_best;
+    int32_t pad_;
+    int64_t sample_sum;   /* Sum over the samples (Mean = sample_sum / samples) */
+    int64_t start_f;      /* f of the derivative start                          */
+    int64_t passers;      /* iterations whose candidate passed the screen       */
+    int64_t flips;        /* flips of all ascents                               */
+    int64_t improvements; /* times the incumbent was replaced                   */
+} orc_seq_out;
+
+/*
+ * The main loop of Fig. 2 as printed: one candidate per iteration.
+ *   Mean: average objective of `samples` random solutions (EvaluateRandomStarts;
+ *         sample s is orc_random_solution(run_seed, g = 0, S = samples, s));
+ *   starting solution x0: the first-derivative solution; Max starts at f(x0)
+ *         (CalculateFirstDerivativeSolution, CalculateT);
+ *   iteration 0 takes x0 itself; iteration i >= 1 diversifies the incumbent
+ *         (x0 while there is none) with Glover's generator, the step tied to
+ *         the loop counter: c = i - 1, h = (c / 2 mod H) + 1, variables
+ *         j = 0, h, 2h, ... flipped, and the result complemented when c is odd;
+ *   screen: f > T = Mean + lambda (Max - Mean), decided exactly as
+ *         den * samples * f > (den - num) * Sum + num * samples * Max;
+ *   a passer is ascended (steepest 1-flip, max_flips) and replaces the
+ *         incumbent when its f is larger (strictly) or there is none; then
+ *         Max = the new incumbent value (UpdateBestAndT).
+ * The readings: lambda is a fixed rational (the printed lambda = Max / Mean
+ * would put T above Max); the incumbent is the solution diversified.
+ * f_dump (I entries, may be NULL) receives each iteration's f before ascent;
+ * history (history_cap pairs, may be NULL) the (iteration, value) of each
+ * replacement of the incumbent, the first history_cap of them.
+ */
+ORC_API void orc_sequential(int32_t n, const int32_t *Q, const orc_seq_params *pr, orc_seq_out *out,
+                            uint64_t *best_x, int64_t *f_dump, int64_t *history, int64_t history_cap,
+                            int32_t threads)
+{
+    const int64_t W = words_for(n), Ms = pr->samples;
+    uint64_t *X = (uint64_t *)calloc((size_t)(Ms * W), 8);
+    int64_t *fs = (int64_t *)calloc((size_t)Ms, 8);
+    uint64_t *x0 = (uint64_t *)calloc((size_t)W, 8);
+    uint64_t *x = (uint64_t *)calloc((size_t)W, 8);
+    memset(out, 0, sizeof(*out));
+
+    /* Mean from random solutions */
+    for (int64_t s = 0; s < Ms; s++) orc_random_solution(n, pr->run_seed, 0, Ms, s, X + s * W);
+    orc_eval(n, Q, X, Ms, fs, threads);
+    int64_t sum = 0;
+    for (int64_t s = 0; s < Ms; s++) sum += fs[s];
+    /* starting solution and the initial Max */
+    orc_derivative_start(n, Q, x0);
+    const int64_t f0 = orc_f(n, Q, x0);
+    int64_t mx = f0, bf = INT64_MIN;
+    int have_best = 0;
+
+    for (int64_t i = 0; i < pr->iterations; i++) {
+        const uint64_t *seed = have_best ? best_x : x0;
+        memcpy(x, seed, (size_t)W * 8);
+        if (i > 0) {
+            const int64_t c = i - 1;
+            const int64_t h = (c / 2) % pr->H + 1;
+            for (int64_t j = 0; j < n; j += h) put_bit(x, j, !get_bit(x, j));
+            if (c % 2)
+                for (int64_t j = 0; j < n; j++) put_bit(x, j, !get_bit(x, j));
+        }
+        int64_t fx = orc_f(n, Q, x);
+        if (f_dump) f_dump[i] = fx;
+        const __int128 lhs = (__int128)pr->lam_den * Ms * fx;
+        const __int128 rhs = (__int128)(pr->lam_den - pr->lam_num) * sum + (__int128)pr->lam_num * Ms * mx;
+        if (!(lhs > rhs)) continue;
+        out->passers++;
+        out->flips += orc_ascent(n, Q, x, &fx, pr->max_flips, 0);
+        if (!have_best || fx > bf) {
+            have_best = 1;
+            bf = fx;
+            memcpy(best_x, x, (size_t)W * 8);
+            mx = bf;
+            if (history && out->improvements < history_cap) {
+                history[2 * out->improvements] = i;
+                history[2 * out->improvements + 1] = fx;
+            }
+            out->improvements++;
+        }
+    }
+    out->best_f = bf;
+    out->have_best = have_best;
+    out->sample_sum = sum;
+    out->start_f = f0;
+    free(X); free(fs); free(x0); free(x);
 }
