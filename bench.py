@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-lam-sweep", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-blend", action="store_true")
+    ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-active", type=int, default=32)
@@ -289,6 +290,39 @@ def batched_bench(ctx, ubqp, torch, count=64, G=6, warm=2, seed=4):
                          "(hi/lo int8 planes), M=4096, H=10, lambda=1/2")
 
 
+def sequential_bench(ctx, CONFIGS, make_instance, prob7000, Q7000, c7000):
+    """The main loop of Fig. 2 as printed, 2500 iterations and Mean over 1000 random
+    solutions, on the paper's two instance shapes: n=2500 at density 0.1 (ORLIB)
+    and n=7000 at density 0.5 (Palubeckis p7000).  Reports the whole loop's time,
+    iterations per second and the time of each replacement of the incumbent."""
+    out = {}
+    c2 = CONFIGS["cfg2"]
+    shapes = [("n2500_d0.1", make_instance(c2["n"], c2["density"], c2["lo"], c2["hi"], c2["inst_seed"]), None,
+               c2["run_seed"]),
+              ("n7000_d0.5", Q7000, prob7000, c7000["run_seed"])]
+    for name, Q, prob, rs in shapes:
+        prob = prob if prob is not None else ctx.problem(Q)
+        kw = dict(iterations=2500, samples=1000, H=0, lam_num=1, lam_den=2, run_seed=rs)
+        ctx.sequential(prob, **dict(kw, iterations=300))  # warm-up
+        t0 = time.perf_counter()
+        r = ctx.sequential(prob, **kw)
+        wall = (time.perf_counter() - t0) * 1e3
+        out[name] = dict(iterations=kw["iterations"], samples=kw["samples"], **{"lambda": "1/2"},
+                         ms_loop=r["ms_device"], ms_loop_events=r["ms"], ms_call=wall,
+                         iterations_per_s=kw["iterations"] / (r["ms_device"] * 1e-3),
+                         best_f=r["best_f"], improvements=r["improvements"], passers=r["passers"],
+                         flips=r["flips"], windows=r["windows"], evaluated=r["evaluated"],
+                         last_improvement_iteration=int(r["history"][-1, 0]) if len(r["history"]) else None,
+                         improvement_ms=[round(float(t), 3) for t in r["history_ms"]],
+                         improvement_f=[int(v) for v in r["history"][:, 1]])
+        log(f"[seq] {name}: {kw['iterations']} iterations in {r['ms_device']:.2f} ms (stream events "
+            f"{r['ms']:.2f} ms, {wall:.2f} ms with set-up), "
+            f"{r['improvements']} improvements (last at iteration {out[name]['last_improvement_iteration']}, "
+            f"{out[name]['improvement_ms'][-1] if r['improvements'] else 0:.2f} ms), best f {r['best_f']}, "
+            f"{r['passers']} passers, {r['windows']} windows, {r['evaluated']} candidates evaluated")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -382,6 +416,11 @@ def main():
         log(f"[bench] blending: {tb:.3f} ms/generation, diversify {blend['phases_ms']['diversify']:.4f} ms, "
             f"P={stb[:, 2].mean():.0f} flips={stb[:, 3].mean():.0f}, best f {rbr['best_f']} "
             f"(Glover {res['best_f']}) after {Wm + K} generations")
+
+    # ---- the paper's own loop: one candidate per iteration (Fig. 2) ------------------
+    seq = None
+    if not args.no_seq:
+        seq = sequential_bench(ctx, CONFIGS, make_instance, prob, Q, c)
 
     # ---- evaluation alone (the batched exact objective) ------------------------
     X = random_candidates(M, n, 5)
@@ -504,6 +543,7 @@ def main():
         "e1_replica": e1_rep,
         "lambda_sweep": lam_sweep,
         "blend": blend,
+        "sequential": seq,
         "batched": batched,
         "serving": serving,
     }

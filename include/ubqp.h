@@ -246,6 +246,77 @@ UBQP_API int ubqp_multistart(ubqp_ctx *ctx, const ubqp_problem *prob, const ubqp
                              int64_t *f_dump_d, ubqp_result *result);
 
 /*
+ * The main loop of Fig. 2 as printed: one candidate per iteration.
+ *   Mean: the average objective of `samples` random solutions
+ *     (EvaluateRandomStarts; word w of sample s is SplitMix64 output s W + w of
+ *     run_seed, bits >= n cleared);
+ *   x0: the first-derivative starting solution; Max starts at f(x0);
+ *   iteration 0 takes x0; iteration i >= 1 diversifies the incumbent (x0 while
+ *     there is none) with Glover's generator, the step tied to the loop counter:
+ *     with c = i - 1, variables j = 0, h, 2h, ... flip for h = (c / 2 mod H) + 1,
+ *     and the result is complemented when c is odd;
+ *   a candidate with f > T = Mean + lambda (Max - Mean) (decided exactly, as
+ *     den * samples * f > (den - num) * Sum + num * samples * Max) is ascended
+ *     (steepest 1-flip, at most max_flips); when its value beats the incumbent
+ *     (strictly, or there is none) it becomes the incumbent and Max its value
+ *     (UpdateBestAndT).
+ * lambda is a fixed rational (the printed lambda = Max / Mean would put T above
+ * Max).  The device works a window of up to `batch` iterations ahead: their
+ * candidates are built from the current incumbent, evaluated together,
+ * screened in order and every passer ascended; the first passer that replaces
+ * the incumbent closes the window, and the iterations after it are built again
+ * from the new incumbent in the next window.  The result therefore equals the
+ * one-candidate-at-a-time loop for every window size.
+ */
+#define UBQP_SEQ_MAX_SAMPLES (1 << 20)
+#define UBQP_SEQ_MAX_BATCH 8192
+
+typedef struct {
+    int64_t iterations;     /* I >= 1: iterations of the main loop                            */
+    int32_t samples;        /* random solutions behind Mean, 1..UBQP_SEQ_MAX_SAMPLES           */
+    int32_t H;              /* cycle of the diversification step, >= 1; 0 means n              */
+    int32_t lam_num;        /* lambda = lam_num / lam_den, 0 <= lam_num <= lam_den              */
+    int32_t lam_den;
+    int32_t max_flips;      /* flips per ascent, 0 = until a 1-flip local optimum             */
+    int32_t batch;          /* largest window, 1..UBQP_SEQ_MAX_BATCH, 0 = 4096 (speed only)    */
+    uint32_t flags;         /* UBQP_NO_GRAPH, or 0                                             */
+    int32_t pad_;
+    uint64_t run_seed;      /* SplitMix64 seed of the samples                                  */
+    double time_budget_ms;  /* > 0: stop launching windows once this much time has passed      */
+} ubqp_seq_params;
+
+typedef struct {
+    uint64_t *best_x_host;   /* out, W words (may be NULL)                                      */
+    int64_t *history_host;   /* out, history_cap x 2: (iteration, value) of the first           */
+                             /*   history_cap replacements of the incumbent (may be NULL)        */
+    double *history_ms_host; /* out, history_cap: ms from the start of the loop to the commit of */
+                             /*   each replacement, device wall clock (may be NULL)             */
+    int64_t history_cap;     /* entries of the history arrays                                    */
+    int64_t *f_dump_d;       /* device, `iterations` int64: each iteration's f before ascent     */
+                             /*   (may be NULL)                                                  */
+    int64_t best_f;          /* out: incumbent value (INT64_MIN if none)                         */
+    int32_t have_best;       /* out                                                              */
+    int32_t pad_;
+    int64_t iterations_done; /* out: I, or fewer when the time budget ended the loop             */
+    int64_t sample_sum;      /* out: Sum of the samples' objectives (Mean = sample_sum / samples) */
+    int64_t start_f;         /* out: f(x0)                                                       */
+    int64_t passers;         /* out: iterations whose candidate passed the screen                */
+    int64_t flips;           /* out: flips of their ascents                                      */
+    int64_t improvements;    /* out: replacements of the incumbent                               */
+    int64_t windows;         /* out: windows evaluated                                           */
+    int64_t evaluated;       /* out: candidates evaluated, discarded look-ahead included         */
+    double ms;               /* out: time of the loop after the set-up, from stream events        */
+                             /*   (includes the windows queued after the last one, which idle)   */
+    double ms_device;        /* out: device wall clock from the start of the loop to the commit  */
+                             /*   of the last window                                             */
+} ubqp_seq_result;
+
+/* Synchronous.  Errors: UBQP_EINVAL (parameters, flags other than UBQP_NO_GRAPH),
+ * UBQP_ENOMEM, UBQP_EDEVICE (the ascent's safety bound). */
+UBQP_API int ubqp_sequential(ubqp_ctx *ctx, const ubqp_problem *prob, const ubqp_seq_params *params,
+                             ubqp_seq_result *result);
+
+/*
  * Batched form: `count` independent multi-start runs (instance i: probs[i],
  * params[i]; sizes, coefficient widths and parameters may all differ, the
  * generation count G must be equal) advanced together.  Each step of a

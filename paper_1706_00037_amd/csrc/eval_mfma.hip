@@ -113,8 +113,10 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
         nt = (nt & 1) ? (nt >> 1) : a.n_tiles - 1 - (nt >> 1);
     }
 
+    // rows in use: the gathered list's device length (Y / key epilogues), or for
+    // the row dot an optional device row count (rows beyond it are skipped)
     int64_t Mrows = a.M;
-    if (STORE_Y) { const int64_t k = *a.nrows_d - a.offset; Mrows = k < a.M ? k : a.M; }
+    if (STORE_Y || a.nrows_d) { const int64_t k = *a.nrows_d - a.offset; Mrows = k < a.M ? k : a.M; }
     const int64_t m0 = (int64_t)mt * BM;
     if (m0 >= Mrows) return;
     const int n0 = nt * BN;

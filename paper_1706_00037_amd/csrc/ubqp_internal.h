@@ -170,7 +170,8 @@ struct EvalArgs {            // int8 matrix-core contraction Y = X Q and its epi
     int64_t M;               // rows (or capacity of the gather list)
     const int32_t *rows;     // gather list (Y / key epilogues), already offset to the chunk
     int64_t x_rows;          // rows of X (gather targets outside [0, x_rows) read as zero)
-    const int64_t *nrows_d;  // device length of the whole list (Y / key epilogues)
+    const int64_t *nrows_d;  // device length of the whole list (Y / key epilogues); row dot: null,
+                             // or a device count of the rows to evaluate (the rest are skipped)
     int64_t offset;          // first list entry of this chunk
     int64_t *f;              // row-dot output
     int32_t *Y;              // Y output [planes][M][n_pad] or keys [M][n_pad]

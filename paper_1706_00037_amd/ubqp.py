@@ -47,6 +47,23 @@ class Result(ctypes.Structure):
                 ("gen_ms_host", ctypes.c_void_p), ("phase_ms_host", ctypes.c_void_p)]
 
 
+class SeqParams(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("samples", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("lam_num", ctypes.c_int32), ("lam_den", ctypes.c_int32), ("max_flips", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("flags", ctypes.c_uint32), ("pad_", ctypes.c_int32),
+                ("run_seed", ctypes.c_uint64), ("time_budget_ms", ctypes.c_double)]
+
+
+class SeqResult(ctypes.Structure):
+    _fields_ = [("best_x_host", ctypes.c_void_p), ("history_host", ctypes.c_void_p),
+                ("history_ms_host", ctypes.c_void_p), ("history_cap", ctypes.c_int64), ("f_dump_d", ctypes.c_void_p),
+                ("best_f", ctypes.c_int64), ("have_best", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("iterations_done", ctypes.c_int64), ("sample_sum", ctypes.c_int64), ("start_f", ctypes.c_int64),
+                ("passers", ctypes.c_int64), ("flips", ctypes.c_int64), ("improvements", ctypes.c_int64),
+                ("windows", ctypes.c_int64), ("evaluated", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("ms_device", ctypes.c_double)]
+
+
 def declared_functions() -> list[str]:
     """Names of the functions declared in include/ubqp.h."""
     text = open(HEADER).read()
@@ -74,6 +91,7 @@ def load():
         "ubqp_problem_info": [P, P, P, P],
         "ubqp_diversify": [P, i32, P, i64, i32, P, i64],
         "ubqp_blend": [P, i32, P, i64, i64, i64, u64, P],
+        "ubqp_sequential": [P, P, P, P],
         "ubqp_eval": [P, P, P, i64, P],
         "ubqp_eval_variant": [P, P, P, i64, P, i32],
         "ubqp_tune_eval": [P, P, i64, ctypes.POINTER(i32), P],
@@ -456,6 +474,24 @@ class Context:
             return [b.result(i) for i in range(len(probs))]
         finally:
             b.close()
+
+    def sequential(self, prob: Problem, iterations, samples, H, lam_num, lam_den, max_flips=0, batch=0, run_seed=0,
+                   flags=0, time_budget_ms=0.0, f_dump=None, history_cap=1 << 16) -> dict:
+        """The main loop of Fig. 2 one candidate per iteration (ubqp_sequential)."""
+        sp = SeqParams(iterations, samples, H, lam_num, lam_den, max_flips, batch, flags, 0, run_seed,
+                       float(time_budget_ms))
+        bx = np.zeros(prob.W, np.uint64)
+        hist = np.zeros((history_cap, 2), np.int64)
+        hms = np.zeros(history_cap, np.float64)
+        dump = self._t(f_dump, self.torch.int64, iterations, "f_dump") if f_dump is not None else None
+        r = SeqResult(bx.ctypes.data, hist.ctypes.data, hms.ctypes.data, history_cap, dump)
+        self._call("ubqp_sequential", self.h, prob.h, ctypes.byref(sp), ctypes.byref(r))
+        k = min(int(r.improvements), history_cap)
+        return dict(best_f=int(r.best_f), have_best=bool(r.have_best), best_x=bx, iterations_done=int(r.iterations_done),
+                    sample_sum=int(r.sample_sum), start_f=int(r.start_f), passers=int(r.passers), flips=int(r.flips),
+                    improvements=int(r.improvements), windows=int(r.windows), evaluated=int(r.evaluated),
+                    ms=float(r.ms), ms_device=float(r.ms_device), history=hist[:k].copy(),
+                    history_ms=hms[:k].copy())
 
     def server(self, pool_bytes: int, max_active: int) -> Server:
         return Server(self, pool_bytes, max_active)

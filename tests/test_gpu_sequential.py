@@ -1,0 +1,126 @@
+"""Parity of the sequential main loop (Fig. 2, one candidate per iteration;
+ubqp_sequential through the C ABI) with the oracle's orc_sequential.
+
+The device works windows of look-ahead iterations; the result must be that of
+the one-at-a-time loop whatever the window size, so every case is also run at
+several window sizes.  Every comparison is bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1706_00037_amd.inputs import CONFIGS, make_instance, unpack_bits
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ub():
+    from paper_1706_00037_amd import ubqp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ubqp
+
+
+@pytest.fixture(scope="module")
+def ctx(ub):
+    return ub.Context(0)
+
+
+def _same(r, o, tag):
+    for k in ("have_best", "best_f", "sample_sum", "start_f", "passers", "flips", "improvements"):
+        assert r[k] == o[k], (tag, k, r[k], o[k])
+    assert np.array_equal(r["history"], o["history"]), tag
+    if o["have_best"]:
+        assert np.array_equal(r["best_x"], o["best_x"]), tag
+
+
+CASES = [
+    # n, density, lo, hi, iterations, samples, H, lambda, max_flips
+    (300, 0.5, -100, 100, 400, 100, 0, (1, 2), 0),
+    (129, 0.3, -32768, 32767, 300, 50, 20, (3, 10), 0),          # two planes
+    (64, 0.9, -128, 127, 257, 7, 1, (4, 5), 0),
+    (500, 0.1, -100, 100, 600, 1000, 250, (1, 2), 5),
+    (1, 1.0, -100, 100, 9, 5, 0, (1, 2), 0),
+    (90, 0.5, -100, 100, 200, 30, 45, (1, 1), 0),                  # every passer improves
+    (1100, 0.2, -100, 100, 300, 200, 0, (1, 2), 0),
+]
+
+
+@pytest.mark.parametrize("c", CASES)
+def test_sequential_matches_oracle(ctx, c):
+    n, d, lo, hi, I, Ms, H, lam, mf = c
+    Q = make_instance(n, d, lo, hi, 4200 + n)
+    prob = ctx.problem(Q)
+    kw = dict(iterations=I, samples=Ms, lam_num=lam[0], lam_den=lam[1], max_flips=mf, run_seed=17)
+    o = oracle.sequential(Q, H=H if H else n, threads=8, **kw)
+    dump = torch.zeros(I, dtype=torch.int64, device="cuda")
+    r = ctx.sequential(prob, H=H, f_dump=dump, **kw)
+    _same(r, o, c)
+    assert r["iterations_done"] == I
+    assert np.array_equal(dump.cpu().numpy(), o["f_dump"])
+    assert r["evaluated"] >= I and r["windows"] >= 1
+
+
+@pytest.mark.parametrize("batch", [1, 7, 256, 300, 8192])
+def test_result_does_not_depend_on_the_window(ctx, batch):
+    Q = make_instance(400, 0.3, -100, 100, 55)
+    prob = ctx.problem(Q)
+    kw = dict(iterations=700, samples=100, H=0, lam_num=1, lam_den=2, run_seed=3)
+    o = oracle.sequential(Q, **dict(kw, H=400), threads=8)
+    r = ctx.sequential(prob, batch=batch, **kw)
+    _same(r, o, batch)
+
+
+def test_graph_and_direct_launches_agree(ctx, ub):
+    Q = make_instance(700, 0.3, -100, 100, 56)
+    prob = ctx.problem(Q)
+    kw = dict(iterations=900, samples=200, H=0, lam_num=3, lam_den=10, run_seed=4)
+    a = ctx.sequential(prob, **kw)
+    b = ctx.sequential(prob, flags=ub.UBQP_NO_GRAPH, **kw)
+    for k in ("best_f", "passers", "flips", "improvements", "windows", "evaluated"):
+        assert a[k] == b[k], k
+    assert np.array_equal(a["best_x"], b["best_x"]) and np.array_equal(a["history"], b["history"])
+
+
+def test_history_times_are_ordered(ctx):
+    Q = make_instance(500, 0.3, -100, 100, 57)
+    r = ctx.sequential(ctx.problem(Q), iterations=600, samples=100, H=0, lam_num=1, lam_den=2, run_seed=5)
+    t = r["history_ms"]
+    assert len(t) == r["improvements"] > 0
+    assert (t >= 0).all() and (np.diff(t) >= 0).all() and t[-1] <= r["ms_device"] <= r["ms"] + 0.05
+
+
+def test_time_budget_stops_early_on_a_prefix(ctx):
+    """A budget ends the loop between windows; what was done is the prefix of the
+    full trajectory."""
+    Q = make_instance(2000, 0.1, -100, 100, 58)
+    prob = ctx.problem(Q)
+    kw = dict(samples=100, H=0, lam_num=1, lam_den=2, run_seed=6)
+    part = ctx.sequential(prob, iterations=200000, time_budget_ms=1e-3, **kw)
+    assert 1 <= part["iterations_done"] < 200000
+    full = ctx.sequential(prob, iterations=part["iterations_done"], **kw)
+    assert full["best_f"] == part["best_f"] and np.array_equal(full["history"], part["history"])
+    assert full["passers"] == part["passers"] and full["flips"] == part["flips"]
+
+
+def test_full_size_orlib_shape_matches_oracle(ctx):
+    """n=2500, density 0.1, 2500 iterations: the shape of the paper's ORLIB runs,
+    compared whole with the oracle."""
+    c = CONFIGS["cfg2"]
+    n = c["n"]
+    Q = make_instance(n, c["density"], c["lo"], c["hi"], c["inst_seed"])
+    kw = dict(iterations=2500, samples=1000, lam_num=1, lam_den=2, run_seed=c["run_seed"])
+    o = oracle.sequential(Q, H=n, threads=8, **kw)
+    r = ctx.sequential(ctx.problem(Q), H=0, **kw)
+    _same(r, o, "orlib shape")
+    assert oracle.f(Q, r["best_x"]) == r["best_f"] and (oracle.delta(Q, r["best_x"]) <= 0).all()
+
+
+def test_bad_parameters_rejected(ctx, ub):
+    prob = ctx.problem(make_instance(50, 0.5, -100, 100, 1))
+    good = dict(iterations=10, samples=10, H=0, lam_num=1, lam_den=2)
+    for bad in (dict(iterations=0), dict(samples=0), dict(H=-1), dict(lam_num=3), dict(batch=8193),
+                dict(flags=ub.UBQP_BLEND), dict(time_budget_ms=-1.0), dict(max_flips=-1)):
+        with pytest.raises(ub.UbqpError):
+            ctx.sequential(prob, **dict(good, **bad))
