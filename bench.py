@@ -441,6 +441,9 @@ def main():
     useful_ops = 2.0 * M * n * n
     exec_ops = 2.0 * M * n_pad * n_pad
     log(f"[bench] eval alone {eval_ms:.3f} ms: {useful_ops / eval_ms / 1e9:.1f} TOP/s useful")
+    mfma_meas = ctx.mfma_peak()
+    log(f"[bench] int8 MFMA rate sustained on this device (registers only): {mfma_meas:.0f} TOP/s; the "
+        f"evaluation executes {useful_ops / 2 / eval_ms / 1e9 / mfma_meas:.3f} of it")
 
     # ---- roofline of the dominant phase ------------------------------------------
     dom = max((k for k in phase_mean if k != "ascent_kernel"), key=phase_mean.get)
@@ -539,6 +542,9 @@ def main():
                       "useful_tops": useful_ops / eval_ms / 1e9, "dense_padded_tops": exec_ops / eval_ms / 1e9,
                       "frac_int8_peak": useful_ops / eval_ms / 1e9 / INT8_PEAK_TOPS,
                       "executed_lower_triangle_tops": useful_ops / 2 / eval_ms / 1e9,
+                      "mfma_peak_measured_tops": mfma_meas,
+                      "frac_measured_peak_useful": useful_ops / eval_ms / 1e9 / mfma_meas,
+                      "frac_measured_peak_executed": useful_ops / 2 / eval_ms / 1e9 / mfma_meas,
                       "traffic_gb_per_launch": TRAFFIC_GB["eval"]},
         "e1_replica": e1_rep,
         "lambda_sweep": lam_sweep,

@@ -187,6 +187,14 @@ UBQP_API int ubqp_tune_eval(ubqp_ctx *ctx, const ubqp_problem *prob, int64_t M, 
 UBQP_API int ubqp_eval_variant(ubqp_ctx *ctx, const ubqp_problem *prob, const uint64_t *X_d, int64_t M,
                                int64_t *f_d, int32_t variant);
 
+/*
+ * Measurement: the int8 matrix-core rate the device sustains (tera-ops per
+ * second, 2 ops per multiply-add) on v_mfma_i32_32x32x32_i8, the instruction of
+ * the evaluation, with operands in registers, 16 waves per compute unit, best of
+ * three timed launches after a warm-up.  Synchronous.
+ */
+UBQP_API int ubqp_mfma_peak(ubqp_ctx *ctx, double *tops);
+
 
 /*
  * Screening (Pseudocode section): T(lambda) = Mean + lambda (Max - Mean) over

@@ -92,6 +92,7 @@ def load():
         "ubqp_diversify": [P, i32, P, i64, i32, P, i64],
         "ubqp_blend": [P, i32, P, i64, i64, i64, u64, P],
         "ubqp_sequential": [P, P, P, P],
+        "ubqp_mfma_peak": [P, P],
         "ubqp_eval": [P, P, P, i64, P],
         "ubqp_eval_variant": [P, P, P, i64, P, i32],
         "ubqp_tune_eval": [P, P, i64, ctypes.POINTER(i32), P],
@@ -492,6 +493,12 @@ class Context:
                     improvements=int(r.improvements), windows=int(r.windows), evaluated=int(r.evaluated),
                     ms=float(r.ms), ms_device=float(r.ms_device), history=hist[:k].copy(),
                     history_ms=hms[:k].copy())
+
+    def mfma_peak(self) -> float:
+        """Sustained int8 matrix-core rate of the device in TOP/s (ubqp_mfma_peak)."""
+        v = ctypes.c_double()
+        self._call("ubqp_mfma_peak", self.h, ctypes.byref(v))
+        return float(v.value)
 
     def server(self, pool_bytes: int, max_active: int) -> Server:
         return Server(self, pool_bytes, max_active)
