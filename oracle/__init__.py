@@ -70,6 +70,8 @@ def lib():
             "orc_diversify": (None, [i32, P, i64, i32, P, i64]),
             "orc_blend": (None, [i32, P, i64, i64, i64, u64, P]),
             "orc_sequential": (None, [i32, P, P, P, P, P, P, i64, i32]),
+            "orc_relink_path": (i64, [i32, P, P, P, i32, P, P]),
+            "orc_relink_many": (None, [i32, P, P, P, i64, i32, P, P, P, P, i32]),
             "orc_screen": (i64, [P, i64, i32, i32, P, P, P]),
             "orc_delta_recompute": (None, [i32, P, P, P]),
             "orc_delta": (None, [i32, P, P, P]),
@@ -236,3 +238,31 @@ def sequential(Q, iterations, samples, H, lam_num, lam_den, max_flips=0, run_see
     return dict(best_f=out.best_f, best_x=bx, have_best=bool(out.have_best), sample_sum=out.sample_sum,
                 start_f=out.start_f, passers=out.passers, flips=out.flips, improvements=out.improvements,
                 history=hist[:k].copy(), f_dump=fd)
+
+
+def relink_path(Q, x_init, x_guide, mode=0):
+    """Greedy relinking from x_init toward x_guide: (steps, x_mid, f_mid)."""
+    Q = _q(Q)
+    n = Q.shape[0]
+    xi = np.ascontiguousarray(x_init, np.uint64)
+    xg = np.ascontiguousarray(x_guide, np.uint64)
+    xm = np.zeros(words(n), np.uint64)
+    fm = np.zeros(1, np.int64)
+    st = lib().orc_relink_path(n, _p(Q), _p(xi), _p(xg), mode, _p(xm), _p(fm))
+    return int(st), xm, int(fm[0])
+
+
+def relink_many(Q, elite, pairs, max_flips=0, threads=1):
+    """Relinking of pairs (rows of [P, 2] indices into elite), then ascent:
+    dict(X, f_mid, f_out, steps)."""
+    Q = _q(Q)
+    n = Q.shape[0]
+    elite = np.ascontiguousarray(elite, np.uint64)
+    pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+    P = pairs.shape[0]
+    X = np.zeros((P, words(n)), np.uint64)
+    fm = np.zeros(P, np.int64)
+    fo = np.zeros(P, np.int64)
+    st = np.zeros(P, np.int64)
+    lib().orc_relink_many(n, _p(Q), _p(elite), _p(pairs), P, max_flips, _p(X), _p(fm), _p(fo), _p(st), threads)
+    return dict(X=X, f_mid=fm, f_out=fo, steps=st)

@@ -23,6 +23,8 @@
  *   main loop        diversify -> evaluate -> screen -> ascent -> update best
  *                    (Fig. 2), a generation of many candidates at a time, or
  *                    one candidate per iteration as printed (orc_sequential)
+ *   path relinking   the polishing phase the paper names but does not build
+ *                    (greedy relinking, rule read here; orc_relink_path)
  * The readings taken where the paper is silent are listed at each function.
  *
  * Pins that do not come from this file are in tests/test_oracle_*.py.
@@ -499,4 +501,87 @@ ORC_API void orc_sequential(int32_t n, const int32_t *Q, const orc_seq_params *p
     out->sample_sum = sum;
     out->start_f = f0;
     free(X); free(fs); free(x0); free(x);
+}
+
+/* ------------------------------------------------------- path relinking */
+
+/*
+ * Path relinking, the improvement phase the paper names as the one to follow
+ * its initial phase (Introduction, Pseudocode section, Conclusions; Glover,
+ * Laguna & Marti 2000), which the paper does not implement.  The rule read
+ * here is greedy relinking:
+ *   D = the variables where the initiating solution x and the guiding one
+ *       differ; from x, repeatedly flip the k in D with the largest
+ *       Delta_k = f(x xor e_k) - f(x) (the lowest k on ties), improving or
+ *       not, and remove k from D, for |D| - 1 steps (the last flip would reach
+ *       the guiding solution, which is not an intermediate);
+ *   the result is the intermediate of largest f, the earliest on ties (strict
+ *       comparison), and the number of steps to it; none when |D| <= 1.
+ * mode 0 keeps the deltas by the one-column update of orc_ascent, mode 1
+ * recomputes them from their definition after every flip.
+ * Returns the steps to the best intermediate (0: none); x_mid and f_mid
+ * receive it.
+ */
+ORC_API int64_t orc_relink_path(int32_t n, const int32_t *Q, const uint64_t *x_init, const uint64_t *x_guide,
+                                int32_t mode, uint64_t *x_mid, int64_t *f_mid)
+{
+    const int64_t W = words_for(n);
+    uint64_t *x = (uint64_t *)malloc((size_t)W * 8);
+    uint8_t *free_ = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t *d = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * 8);
+    memcpy(x, x_init, (size_t)W * 8);
+    int64_t nd = 0;
+    for (int64_t j = 0; j < n; j++) {
+        free_[j] = get_bit(x_init, j) != get_bit(x_guide, j);
+        nd += free_[j];
+    }
+    if (mode == 1) orc_delta_recompute(n, Q, x, d); else orc_delta(n, Q, x, d);
+    int64_t fx = orc_f(n, Q, x), best = INT64_MIN, best_step = 0;
+    for (int64_t s = 1; s < nd; s++) {
+        int64_t k = -1;
+        for (int64_t i = 0; i < n; i++)
+            if (free_[i] && (k < 0 || d[i] > d[k])) k = i;
+        const int old = get_bit(x, k);
+        put_bit(x, k, !old);
+        free_[k] = 0;
+        fx += d[k];
+        if (fx > best) {
+            best = fx;
+            best_step = s;
+            memcpy(x_mid, x, (size_t)W * 8);
+        }
+        if (mode == 1) {
+            orc_delta_recompute(n, Q, x, d);
+        } else {
+            for (int64_t i = 0; i < n; i++)
+                if (i != k) d[i] += 2 * (int64_t)Q[i * n + k] * (1 - 2 * get_bit(x, i)) * (1 - 2 * old);
+            d[k] = -d[k];
+        }
+    }
+    if (best_step == 0) memcpy(x_mid, x_init, (size_t)W * 8);
+    *f_mid = best;
+    free(x); free(free_); free(d);
+    return best_step;
+}
+
+/*
+ * Relinking of P pairs (initiating, guiding) = (elite[pairs[2p]], elite[pairs[2p+1]]):
+ * X_out row p, f_mid[p], steps[p] from orc_relink_path; then the steepest ascent
+ * (orc_ascent, max_flips) from the intermediate gives f_out[p] and the final
+ * row.  Paths without an intermediate keep the initiating row, and
+ * f_mid = f_out = INT64_MIN.  `threads` only partitions the paths.
+ */
+ORC_API void orc_relink_many(int32_t n, const int32_t *Q, const uint64_t *elite, const int32_t *pairs, int64_t P,
+                             int32_t max_flips, uint64_t *X_out, int64_t *f_mid, int64_t *f_out, int64_t *steps,
+                             int32_t threads)
+{
+    const int64_t W = words_for(n);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads > 0 ? threads : 1)
+    for (int64_t p = 0; p < P; p++) {
+        uint64_t *xo = X_out + p * W;
+        steps[p] = orc_relink_path(n, Q, elite + (int64_t)pairs[2 * p] * W, elite + (int64_t)pairs[2 * p + 1] * W, 0,
+                                   xo, &f_mid[p]);
+        f_out[p] = f_mid[p];
+        if (steps[p] > 0) orc_ascent(n, Q, xo, &f_out[p], max_flips, 0);
+    }
 }
