@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-blend", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
+    ap.add_argument("--no-relink", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-active", type=int, default=32)
@@ -323,6 +324,46 @@ def sequential_bench(ctx, CONFIGS, make_instance, prob7000, Q7000, c7000):
     return out
 
 
+def relink_bench(ctx, ubqp, torch, prob, n, M, H, lam_num, lam_den, E=16, G=3):
+    """The polishing phase: E incumbents of independent short runs (G generations
+    each, run seeds 100..100+E-1) form the elite set; every ordered pair is
+    relinked and the intermediate ascended.  Walk flips = sum over paths of
+    (Hamming distance - 1); each streams one row of the ascent matrix."""
+    runs = [ctx.multistart(prob, M=M, H=H, lam_num=lam_num, lam_den=lam_den, G=G, run_seed=100 + k)
+            for k in range(E)]
+    elite = np.stack([r["best_x"] for r in runs])
+    best_elite = max(int(r["best_f"]) for r in runs)
+    pairs = np.array([(a, b) for a in range(E) for b in range(E) if a != b], np.int32)
+    P = len(pairs)
+    ed = torch.from_numpy(elite.view(np.int64)).cuda()
+    pd = torch.from_numpy(pairs).cuda()
+    X = torch.empty((P, prob.W), dtype=torch.int64, device="cuda")
+    fm = torch.empty(P, dtype=torch.int64, device="cuda")
+    fo = torch.empty(P, dtype=torch.int64, device="cuda")
+    st = torch.empty(P, dtype=torch.int32, device="cuda")
+    ctx.relink(prob, ed, pd, X, fm, fo, st)  # warm-up
+    ctx.sync()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.relink(prob, ed, pd, X, fm, fo, st)
+    e1.record(stream)
+    ctx.sync()
+    ms = e0.elapsed_time(e1)
+    bits = np.unpackbits(elite.view(np.uint8), axis=1, bitorder="little")
+    dist = np.array([int((bits[a] != bits[b]).sum()) for a, b in pairs])
+    walk = int(np.maximum(dist - 1, 0).sum())
+    fo_h = fo.cpu().numpy()
+    out = dict(elite=E, generations_per_elite_run=G, paths=P, ms=ms, walk_flips=walk,
+               walk_flips_per_s=walk / (ms * 1e-3), walk_gb_per_s=walk * n / (ms * 1e-3) / 1e9,
+               mean_distance=float(dist.mean()), best_elite_f=best_elite, best_relinked_f=int(fo_h.max()),
+               improved_paths=int((fo_h > best_elite).sum()))
+    log(f"[relink] {E} elite solutions (n={n}), {P} paths: {ms:.2f} ms, {walk} walk flips "
+        f"({out['walk_gb_per_s']:.0f} GB/s of rows), best elite f {best_elite}, best relinked "
+        f"{out['best_relinked_f']} ({out['improved_paths']} paths beat the elite)")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -421,6 +462,11 @@ def main():
     seq = None
     if not args.no_seq:
         seq = sequential_bench(ctx, CONFIGS, make_instance, prob, Q, c)
+
+    # ---- path relinking of an elite set at the headline size -------------------------
+    relink = None
+    if not args.no_relink:
+        relink = relink_bench(ctx, ubqp, torch, prob, n, M, H, lam_num, lam_den)
 
     # ---- evaluation alone (the batched exact objective) ------------------------
     X = random_candidates(M, n, 5)
@@ -550,6 +596,7 @@ def main():
         "lambda_sweep": lam_sweep,
         "blend": blend,
         "sequential": seq,
+        "relink": relink,
         "batched": batched,
         "serving": serving,
     }

@@ -276,6 +276,29 @@ UBQP_API int ubqp_multistart(ubqp_ctx *ctx, const ubqp_problem *prob, const ubqp
  * from the new incumbent in the next window.  The result therefore equals the
  * one-candidate-at-a-time loop for every window size.
  */
+/*
+ * Path relinking, the improvement phase the paper names to follow its initial
+ * phase (Introduction, Pseudocode section, Conclusions) but does not build;
+ * greedy relinking (Glover, Laguna & Marti 2000) is the rule taken.  Path p goes
+ * from the initiating solution elite_d[pairs_d[2p]] toward the guiding one
+ * elite_d[pairs_d[2p+1]]: the free variables are those where the two differ;
+ * each step flips the free variable with the largest Delta (the lowest index on
+ * ties), improving or not, and retires it, for |D| - 1 steps.  The intermediate
+ * of largest f (the first on ties) is then ascended (steepest 1-flip, at most
+ * max_flips, 0 = to a local optimum).
+ * Outputs, P rows each: X_out_d (P x W) the ascended intermediate, f_mid_d its
+ * value before and f_out_d after the ascent, steps_d its distance from the
+ * initiating solution.  A path whose two solutions differ in at most one
+ * variable has no intermediate: steps 0, f_mid = f_out = INT64_MIN, X_out the
+ * initiating solution.  elite_d: E x W; pairs_d: P x 2 int32, each in [0, E)
+ * (others are skipped and reported as UBQP_EDEVICE by the next ubqp_sync).
+ * Asynchronous on the context's stream; uses a workspace of
+ * planes x min(P, 4096) x n_pad x 4 bytes.
+ */
+UBQP_API int ubqp_relink(ubqp_ctx *ctx, const ubqp_problem *prob, const uint64_t *elite_d, int64_t E,
+                         const int32_t *pairs_d, int64_t P, int32_t max_flips, uint64_t *X_out_d, int64_t *f_mid_d,
+                         int64_t *f_out_d, int32_t *steps_d);
+
 #define UBQP_SEQ_MAX_SAMPLES (1 << 20)
 #define UBQP_SEQ_MAX_BATCH 8192
 

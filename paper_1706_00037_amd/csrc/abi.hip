@@ -76,7 +76,7 @@ int ubqp_check_flag(ubqp_ctx *ctx)
         hipLaunchKernelGGL(zero_i32, dim3(1), dim3(1), 0, ctx->stream, ctx->err_flag);
         UBQP_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         return ubqp_fail(ctx, UBQP_EDEVICE, "%s",
-                         (v & 2) ? "ascent skipped a candidate index outside [0, M)"
+                         (v & 2) ? "an index outside its range was skipped (an ascent candidate or a relinking pair)"
                                  : "ascent exceeded its safety bound of flips");
     }
     return UBQP_OK;

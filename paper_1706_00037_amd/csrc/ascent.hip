@@ -430,6 +430,215 @@ __global__ __launch_bounds__(64, AscOcc<NB>::waves) void ascent_i8_batched(const
     for (int64_t p = w0; p < P; p += nw) ascend_i8<NB>(a, p, threadIdx.x);
 }
 
+// ---- greedy path relinking -------------------------------------------------
+// From the initiating solution toward the guiding one: the free variables are
+// those where the two differ; every step flips the free variable with the
+// largest Delta (the lowest column on ties), improving or not, and retires it,
+// for |D| - 1 steps; the intermediate of largest f (the first on ties) is kept.
+// The lane layout and the int32 deltas are those of ascend_i16 for both
+// coefficient widths (the keys of the one-plane layout supply Delta = key >> 8).
+// Retired and fixed columns hold RL_GONE: each later flip moves them by at most
+// 2 |q| <= 65534 and a path has fewer than 8192 flips, so they stay inside
+// [-2.14e9, -1.06e9], below every real Delta (|Delta| < 5.4e8) and clear of
+// int32 overflow.  The best intermediate is kept as a copy of the sign bytes.
+constexpr int32_t RL_GONE = -1600000000;
+
+template <int NB, int PLANES>
+__device__ void relink_path(const RelArgs &a, int64_t p, int lane)
+{
+    constexpr int PL = 16 * NB;
+    const int col_base = lane * PL;
+    const int64_t ii = a.pairs[2 * p], gi = a.pairs[2 * p + 1];
+    uint64_t *xr = a.X + p * a.W;
+    if (ii < 0 || ii >= a.E || gi < 0 || gi >= a.E) {
+        if (lane == 0) {
+            atomicOr(a.err, 2);
+            a.f_mid[p] = INT64_MIN;
+            a.f_out[p] = INT64_MIN;
+            a.steps[p] = 0;
+        }
+        return;
+    }
+    const uint64_t *gr = a.elite + gi * a.W;
+    int nd = 0, pc = 0;
+    for (int w = lane; w < a.W; w += 64) {
+        nd += __popcll(xr[w] ^ gr[w]);
+        pc += __popcll(xr[w]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        nd += __shfl_xor(nd, o);
+        pc += __shfl_xor(pc, o);
+    }
+    v16i dl[NB];
+    uint32_t ss[NB][4];
+    const int64_t ystride = a.P * a.n_pad;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int col0 = col_base + 16 * b;
+        const bool in = col0 < a.n_pad;
+        uint32_t bits = 0, free16 = 0;
+        if (in) {
+            const int w = col0 >> 6;
+            if (w < a.W) {
+                bits = (uint32_t)(xr[w] >> (col0 & 63)) & 0xFFFFu;
+                free16 = (uint32_t)((xr[w] ^ gr[w]) >> (col0 & 63)) & 0xFFFFu;
+            }
+        }
+#pragma unroll
+        for (int t4 = 0; t4 < 4; t4++) {
+            int32_t dv[4] = {0, 0, 0, 0};
+            if (in) {
+                if (PLANES == 1) {
+                    const int4 k = ubqp_ldg16i(a.Y + p * a.n_pad + col0 + 4 * t4);
+                    dv[0] = k.x >> 8; dv[1] = k.y >> 8; dv[2] = k.z >> 8; dv[3] = k.w >> 8;
+                } else {
+                    const int4 v0 = ubqp_ldg16i(a.Y + p * a.n_pad + col0 + 4 * t4);
+                    const int4 v1 = ubqp_ldg16i(a.Y + ystride + p * a.n_pad + col0 + 4 * t4);
+                    const int4 dg = ubqp_ldg16i(a.diag + col0 + 4 * t4);
+                    const int32_t y0[4] = {v0.x, v0.y, v0.z, v0.w}, y1[4] = {v1.x, v1.y, v1.z, v1.w};
+                    const int32_t d[4] = {dg.x, dg.y, dg.z, dg.w};
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        const bool xi = (bits >> (4 * t4 + k)) & 1u;
+                        const int32_t y = (int32_t)a.weight0 * y0[k] + y1[k] + (int32_t)a.bias * pc;
+                        const int32_t g = 2 * y + (xi ? -d[k] : d[k]);
+                        dv[k] = xi ? -g : g;
+                    }
+                }
+            }
+            uint32_t sw = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int t = 4 * t4 + k;
+                const bool fr = in && col0 + t < a.n && ((free16 >> t) & 1u);
+                dl[b][t] = fr ? dv[k] : RL_GONE;
+                sw |= (((bits >> t) & 1u) ? 0xFFu : 0x01u) << (8 * k);
+            }
+            ss[b][t4] = sw;
+        }
+    }
+
+    uint32_t sb[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) sb[b][r] = ss[b][r];
+    int64_t fv = a.f0[p], best = INT64_MIN;
+    int32_t bstep = 0;
+    for (int s = 1; s < nd; s++) {
+        int32_t bm[NB];
+#pragma unroll
+        for (int b = 0; b < NB; b++) bm[b] = max16(dl[b]);
+        int32_t bl = bm[0];
+#pragma unroll
+        for (int b = 1; b < NB; b++) bl = max(bl, bm[b]);
+        const int32_t V = wave_max_i32(bl);
+        const int lstar = __ffsll((unsigned long long)__ballot(bl == V)) - 1;
+        int bsel = NB - 1;
+#pragma unroll
+        for (int b = NB - 2; b >= 0; b--) bsel = bm[b] == V ? b : bsel;
+        const int bs = __builtin_amdgcn_readlane(bsel, lstar);
+        int tsel = 15;
+        uint32_t sword = 0;
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            if (b == bs) {
+#pragma unroll
+                for (int t = 14; t >= 0; t--) tsel = dl[b][t] == V ? t : tsel;
+            }
+        }
+        const int ts = __builtin_amdgcn_readlane(tsel, lstar);
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                if (b == bs && r == (ts >> 2)) sword = ss[b][r];
+        const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)sword, lstar);
+        const int32_t xk = ((sk >> (8 * (ts & 3))) & 0xFFu) == 0xFFu;  // x_k before the flip
+        const int K = lstar * PL + 16 * bs + ts;
+        const bool own = lane == lstar;
+        const uint32_t sflip = own ? 0xFEu << (8 * (ts & 3)) : 0u;
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            if (b == bs) {
+                const int32_t ko = dl[b][ts];
+                dl[b][ts] = own ? RL_GONE : ko;   // retired from the free set
+#pragma unroll
+                for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts >> 2)) ? sflip : 0u;
+            }
+        }
+        fv += V;
+        if (fv > best) {
+            best = fv;
+            bstep = s;
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) sb[b][r] = ss[b][r];
+        }
+        // Delta_i += 2 d s_i q_ik for i != k, d = 1 - 2 x_k (the ascent matrix has q_kk = 0)
+        const int32_t step = xk ? -2 : 2;
+        if (PLANES == 1) {
+            const int8_t *row = (const int8_t *)a.qa + (int64_t)K * a.ncol_a + col_base;
+            uint4 w[NB];
+#pragma unroll
+            for (int b = 0; b < NB; b++) w[b] = ubqp_ldg16(row + 16 * b);
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                int32_t d[16];
+#pragma unroll
+                for (int t = 0; t < 16; t++) d[t] = dl[b][t];
+                update_keys8(d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], w[b].x, w[b].y, ss[b][0], ss[b][1], step);
+                update_keys8(d[8], d[9], d[10], d[11], d[12], d[13], d[14], d[15], w[b].z, w[b].w, ss[b][2],
+                             ss[b][3], step);
+#pragma unroll
+                for (int t = 0; t < 16; t++) dl[b][t] = d[t];
+            }
+        } else {
+            const int16_t *row = (const int16_t *)a.qa + (int64_t)K * a.ncol_a + col_base;
+            uint4 w[NB][2];
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                w[b][0] = ubqp_ldg16(row + 16 * b);
+                w[b][1] = ubqp_ldg16(row + 16 * b + 8);
+            }
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                int32_t d[16];
+#pragma unroll
+                for (int t = 0; t < 16; t++) d[t] = dl[b][t];
+                update_deltas8(d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], w[b][0].x, w[b][0].y, w[b][0].z,
+                               w[b][0].w, ss[b][0], ss[b][1], step);
+                update_deltas8(d[8], d[9], d[10], d[11], d[12], d[13], d[14], d[15], w[b][1].x, w[b][1].y,
+                               w[b][1].z, w[b][1].w, ss[b][2], ss[b][3], step);
+#pragma unroll
+                for (int t = 0; t < 16; t++) dl[b][t] = d[t];
+            }
+        }
+    }
+    if (bstep > 0) {
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            uint32_t bits = 0;
+#pragma unroll
+            for (int t = 0; t < 16; t++) bits |= (((sb[b][t >> 2] >> (8 * (t & 3))) & 0xFFu) == 0xFFu ? 1u : 0u) << t;
+            const int ci = lane * NB + b;
+            if (ci < 4 * a.W) ((uint16_t *)xr)[ci] = (uint16_t)bits;
+        }
+    }
+    if (lane == 0) {
+        a.f_mid[p] = best;
+        a.f_out[p] = best;
+        a.steps[p] = bstep;
+    }
+}
+
+template <int NB, int PLANES>
+__global__ __launch_bounds__(64, NB <= 4 ? 2 : 1) void relink_kernel(RelArgs a)
+{
+    for (int64_t p = blockIdx.x; p < a.P; p += gridDim.x) relink_path<NB, PLANES>(a, p, threadIdx.x);
+}
+
 #define UBQP_NB_SWITCH(nb, LAUNCH) \
     switch (nb) {                    \
     case 1: LAUNCH(1); break;        \
@@ -504,5 +713,50 @@ hipError_t ubqp_launch_ascent_batch(hipStream_t st, int planes, int nb, const As
     }
 #undef L16
 #undef L8
+    return hipGetLastError();
+}
+
+RelArgs ubqp_relink_args(const ubqp_problem *p, const uint64_t *elite, int64_t E, const int32_t *pairs, int64_t P,
+                         uint64_t *X, const int32_t *Y, const int64_t *f0, int64_t *f_mid, int64_t *f_out,
+                         int32_t *steps, int32_t *err)
+{
+    RelArgs a{};
+    a.qa = p->qa;
+    a.ncol_a = p->ncol_a;
+    a.diag = p->diag;
+    a.n = p->n;
+    a.n_pad = p->n_pad;
+    a.W = p->W;
+    a.planes = p->planes;
+    a.weight0 = p->weight0;
+    a.bias = p->bias;
+    a.elite = elite;
+    a.E = E;
+    a.pairs = pairs;
+    a.P = P;
+    a.X = X;
+    a.Y = Y;
+    a.f0 = f0;
+    a.f_mid = f_mid;
+    a.f_out = f_out;
+    a.steps = steps;
+    a.err = err;
+    return a;
+}
+
+hipError_t ubqp_launch_relink(hipStream_t st, const RelArgs &a)
+{
+    if (a.P <= 0) return hipSuccess;
+    const unsigned waves = (unsigned)(a.P < 8192 ? a.P : 8192);
+    const int nb = (a.n_pad + 1023) / 1024;
+#define L1(NB) hipLaunchKernelGGL((relink_kernel<NB, 1>), dim3(waves), dim3(64), 0, st, a)
+#define L2(NB) hipLaunchKernelGGL((relink_kernel<NB, 2>), dim3(waves), dim3(64), 0, st, a)
+    if (a.planes == 2) {
+        UBQP_NB_SWITCH(nb, L2)
+    } else {
+        UBQP_NB_SWITCH(nb, L1)
+    }
+#undef L1
+#undef L2
     return hipGetLastError();
 }

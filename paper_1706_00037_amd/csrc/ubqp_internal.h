@@ -24,7 +24,7 @@ struct ubqp_ctx {
     std::string err;
     // Growable device workspace of the step-level entry points, one buffer per slot
     // (a multi-start run owns its own device state).
-    enum Slot { WS_PARTIALS, WS_Y, WS_STAGE, WS_TUNE, WS_COUNT };
+    enum Slot { WS_PARTIALS, WS_Y, WS_STAGE, WS_TUNE, WS_RELINK, WS_COUNT };
     void *ws[WS_COUNT] = {};
     size_t ws_bytes[WS_COUNT] = {};
     int32_t *err_flag = nullptr;  // device int32: kernel-side checks (ascent safety cap)
@@ -213,6 +213,24 @@ struct AscArgs {             // steepest 1-flip ascent
     int32_t *err;
 };
 
+struct RelArgs {             // greedy path relinking, one wave per path
+    const void *qa;          // ascent matrix (zero diagonal), int8 or int16 [n_pad][ncol_a]
+    int32_t ncol_a;
+    const int32_t *diag;
+    int32_t n, n_pad, W, planes;
+    int64_t weight0, bias;
+    const uint64_t *elite;   // [E][W]
+    int64_t E;
+    const int32_t *pairs;    // [P][2]: initiating, guiding (this chunk's first pair at index 0)
+    int64_t P;
+    uint64_t *X;             // [P][W]: the initiating rows; receive the best intermediates
+    const int32_t *Y;        // keys (one plane) or Y planes (two) of the initiating rows, [planes][P][n_pad]
+    const int64_t *f0;       // [P] f of the initiating rows
+    int64_t *f_mid, *f_out;  // [P]
+    int32_t *steps;          // [P]
+    int32_t *err;
+};
+
 struct SelArgs {             // incumbent update, next seeds, statistics, generation counter
     int32_t n, W;
     int64_t M, S;
@@ -289,6 +307,10 @@ AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, con
 int ubqp_ascent_nb(const AscArgs &a);
 int64_t ubqp_ascent_waves(const AscArgs &a);
 hipError_t ubqp_launch_ascent(hipStream_t st, const AscArgs &a);
+RelArgs ubqp_relink_args(const ubqp_problem *p, const uint64_t *elite, int64_t E, const int32_t *pairs, int64_t P,
+                         uint64_t *X, const int32_t *Y, const int64_t *f0, int64_t *f_mid, int64_t *f_out,
+                         int32_t *steps, int32_t *err);
+hipError_t ubqp_launch_relink(hipStream_t st, const RelArgs &a);
 hipError_t ubqp_launch_ascent_batch(hipStream_t st, int planes, int nb, const AscArgs *args, const int64_t *prefix,
                                     int count, int64_t waves);
 

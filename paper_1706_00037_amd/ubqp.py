@@ -93,6 +93,7 @@ def load():
         "ubqp_blend": [P, i32, P, i64, i64, i64, u64, P],
         "ubqp_sequential": [P, P, P, P],
         "ubqp_mfma_peak": [P, P],
+        "ubqp_relink": [P, P, P, i64, P, i64, i32, P, P, P, P],
         "ubqp_eval": [P, P, P, i64, P],
         "ubqp_eval_variant": [P, P, P, i64, P, i32],
         "ubqp_tune_eval": [P, P, i64, ctypes.POINTER(i32), P],
@@ -493,6 +494,37 @@ class Context:
                     improvements=int(r.improvements), windows=int(r.windows), evaluated=int(r.evaluated),
                     ms=float(r.ms), ms_device=float(r.ms_device), history=hist[:k].copy(),
                     history_ms=hms[:k].copy())
+
+    def relink(self, prob: Problem, elite, pairs, X_out, f_mid, f_out, steps, max_flips=0):
+        """Greedy path relinking of pairs (P x 2 int32 device tensor of elite row
+        indices) then ascent (ubqp_relink); device tensors in and out."""
+        torch = self.torch
+        W = prob.W
+        E = elite.numel() // W
+        P = pairs.numel() // 2
+        self._call("ubqp_relink", self.h, prob.h, self._t(elite, torch.int64, E * W, "elite"), E,
+                   self._t(pairs, torch.int32, 2 * P, "pairs"), P, max_flips, self._t(X_out, torch.int64, P * W, "X_out"),
+                   self._t(f_mid, torch.int64, P, "f_mid"), self._t(f_out, torch.int64, P, "f_out"),
+                   self._t(steps, torch.int32, P, "steps"))
+
+    def relink_elite(self, prob: Problem, elite, max_flips=0) -> dict:
+        """Every ordered pair of distinct rows of `elite` (numpy uint64 E x W), in
+        row-major order: dict(pairs, X, f_mid, f_out, steps) on the host."""
+        torch = self.torch
+        elite = np.ascontiguousarray(elite, np.uint64)
+        E = elite.shape[0]
+        pairs = np.array([(a, b) for a in range(E) for b in range(E) if a != b], np.int32).reshape(-1, 2)
+        P = pairs.shape[0]
+        ed = torch.from_numpy(elite.view(np.int64)).cuda()
+        pd = torch.from_numpy(pairs).cuda()
+        X = torch.empty((P, prob.W), dtype=torch.int64, device="cuda")
+        fm = torch.empty(P, dtype=torch.int64, device="cuda")
+        fo = torch.empty(P, dtype=torch.int64, device="cuda")
+        st = torch.empty(P, dtype=torch.int32, device="cuda")
+        self.relink(prob, ed, pd, X, fm, fo, st, max_flips)
+        self.sync()
+        return dict(pairs=pairs, X=X.cpu().numpy().view(np.uint64), f_mid=fm.cpu().numpy(), f_out=fo.cpu().numpy(),
+                    steps=st.cpu().numpy())
 
     def mfma_peak(self) -> float:
         """Sustained int8 matrix-core rate of the device in TOP/s (ubqp_mfma_peak)."""
