@@ -3,7 +3,7 @@
 //
 // One generation of the multi-start loop of Fig. 2 is a fixed sequence of
 // launches, each covering every instance of a set:
-//   diversify -> eval_init + eval (row dot) -> [f dump] -> screen ->
+//   diversify -> eval_init + eval (row dot) -> [f dump] -> screen -> ascent order ->
 //   per passer chunk and (planes, 16-column blocks) group: Delta init + ascent ->
 //   incumbent, ranking, seed fill, generation counter.
 // A launch table holds, for one step, each instance's kernel arguments and the
@@ -21,7 +21,7 @@ inline size_t ubqp_align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Offsets of one instance's device state inside its allocation.
 struct InstLayout {
-    size_t seeds, X, f, flips, idx, rank, scal, bestx, stats, part, err, Y, total;
+    size_t seeds, X, f, flips, idx, oidx, rank, scal, bestx, stats, part, err, Y, total;
     int64_t S, cap;
 };
 InstLayout ubqp_inst_layout(const ubqp_problem *p, const ubqp_params *pr);
@@ -95,6 +95,7 @@ struct GenTables {
     Table<EvalArgs> einit;
     std::vector<EvalGroup> ev;
     Table<ScreenArgs> scr;
+    Table<OrdArgs> ord;                 // one block per instance
     Table<SelArgs> sel_cand, sel_seed;  // same arguments, two prefixes
     Table<SelArgs> init;                // generation-0 seeds of the joining instances
     std::vector<Chunk> chunks;

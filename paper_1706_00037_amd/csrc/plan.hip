@@ -29,6 +29,7 @@ InstLayout ubqp_inst_layout(const ubqp_problem *p, const ubqp_params *pr)
     L.f = take((size_t)M * 8);
     L.flips = take((size_t)M * 4);
     L.idx = take((size_t)M * 4);
+    L.oidx = take((size_t)M * 4);
     L.rank = take((size_t)M * 4);
     L.scal = take(sizeof(ubqp_scal));
     L.bestx = take((size_t)W * 8);
@@ -75,6 +76,7 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
         const ScreenArgs sa = ubqp_screen_args(f, pr.M, pr.lam_num, pr.lam_den, idx, &sc->npass, sc->sum_max,
                                                r.at<void>(L.part));
         scr.add(sa, sa.nblk);
+        ord.add(OrdArgs{f, idx, &sc->npass, r.at<int32_t>(L.oidx)}, 1);
         if (r.dump) has_dump = true;
         const SelArgs sl = ubqp_sel_args(p->n, pr.M, L.S, pr.run_seed, X, f, flips, idx, r.at<int32_t>(L.rank), sc,
                                          r.at<uint64_t>(L.bestx), seeds, r.at<int64_t>(L.stats),
@@ -96,7 +98,8 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
             if (pr.M <= off) continue;
             const int64_t cap = std::min<int64_t>(pr.M - off, L.cap);
             uint64_t *X = r.at<uint64_t>(L.X);
-            int32_t *idx = r.at<int32_t>(L.idx), *Y = r.at<int32_t>(L.Y);
+            // the ascent takes the passers in the order list (lowest objective first)
+            int32_t *idx = r.at<int32_t>(L.oidx), *Y = r.at<int32_t>(L.Y);
             ubqp_scal *sc = r.at<ubqp_scal>(L.scal);
             const EvalArgs yr = ubqp_yrows_args(p, X, pr.M, idx, &sc->npass, off, cap, Y);
             const AscArgs as = ubqp_ascent_args(p, X, pr.M, idx, &sc->npass, off, cap, Y, r.at<int64_t>(L.f),
@@ -127,6 +130,7 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
     einit.stage(host);
     for (EvalGroup &g : ev) g.t.stage(host);
     scr.stage(host);
+    ord.stage(host);
     sel_cand.stage(host);
     sel_seed.stage(host);
     init.stage(host);
@@ -142,6 +146,7 @@ void GenTables::bind(char *dev)
     einit.bind(dev);
     for (EvalGroup &g : ev) g.t.bind(dev);
     scr.bind(dev);
+    ord.bind(dev);
     sel_cand.bind(dev);
     sel_seed.bind(dev);
     init.bind(dev);
@@ -200,6 +205,7 @@ hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t 
     MARK(2);
     if (t.has_dump) Q(ubqp_launch_dump_batch(st, t.sel_cand.d_args, t.sel_cand.d_pre, n, t.sel_cand.total()));
     Q(ubqp_launch_screen_batch(st, t.scr.d_args, t.scr.d_pre, n, t.scr.total()));
+    Q(ubqp_launch_order_batch(st, t.ord.d_args, t.ord.count()));
     MARK(3);
     int lanes = 0;
     for (const Chunk &ch : t.chunks) lanes = ch.lane + 1 > lanes ? ch.lane + 1 : lanes;

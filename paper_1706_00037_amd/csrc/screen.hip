@@ -143,7 +143,77 @@ __global__ __launch_bounds__(THR) void screen_scatter_b(const ScreenArgs *args, 
     scatter_body(a, blockIdx.x - prefix[i]);
 }
 
+// Ascent order of the passers: lowest objective first, in power-of-two-wide
+// buckets of the objective range, so that the candidates furthest below a local
+// optimum (the longest flip chains) are taken first and short chains fill in
+// behind them.  Only the order in which the ascent's waves take candidates
+// changes; every candidate's result is the same in any order.
+constexpr int ORD_THR = 1024;
+constexpr int ORD_BUCKETS = 1024;
+
+__global__ __launch_bounds__(ORD_THR) void order_batched(const OrdArgs *args, int count)
+{
+    __shared__ int32_t start[ORD_BUCKETS];
+    __shared__ int64_t lo_w[ORD_THR / 64], hi_w[ORD_THR / 64];
+    __shared__ int32_t wsum[ORD_THR / 64];
+    if ((int)blockIdx.x >= count) return;
+    const OrdArgs a = args[blockIdx.x];
+    const int64_t P = *a.npass;
+    if (P <= 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (int64_t p = threadIdx.x; p < P; p += ORD_THR) {
+        const int64_t v = a.f[a.idx[p]];
+        lo = v < lo ? v : lo;
+        hi = v > hi ? v : hi;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t l2 = __shfl_xor(lo, o), h2 = __shfl_xor(hi, o);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+    }
+    if (lane == 0) { lo_w[wv] = lo; hi_w[wv] = hi; }
+    start[threadIdx.x] = 0;  // ORD_THR == ORD_BUCKETS
+    __syncthreads();
+    for (int i = 0; i < ORD_THR / 64; i++) {
+        lo = lo_w[i] < lo ? lo_w[i] : lo;
+        hi = hi_w[i] > hi ? hi_w[i] : hi;
+    }
+    // bucket = (v - lo) >> shift with (hi - lo) >> shift < ORD_BUCKETS
+    const uint64_t span = (uint64_t)(hi - lo);
+    int shift = 0;
+    while ((span >> shift) >= (uint64_t)ORD_BUCKETS) shift++;
+    for (int64_t p = threadIdx.x; p < P; p += ORD_THR)
+        atomicAdd(&start[(int)((uint64_t)(a.f[a.idx[p]] - lo) >> shift)], 1);
+    __syncthreads();
+    // exclusive scan of the counts, one bucket per thread
+    const int cnt = start[threadIdx.x];
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int i = 0; i < wv; i++) before += wsum[i];
+    start[threadIdx.x] = before + incl - cnt;
+    __syncthreads();
+    for (int64_t p = threadIdx.x; p < P; p += ORD_THR) {
+        const int32_t c = a.idx[p];
+        const int pos = atomicAdd(&start[(int)((uint64_t)(a.f[c] - lo) >> shift)], 1);
+        a.oidx[pos] = c;
+    }
+}
+
 }  // namespace
+
+hipError_t ubqp_launch_order_batch(hipStream_t st, const OrdArgs *args, int count)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(order_batched, dim3((unsigned)count), dim3(ORD_THR), 0, st, args, count);
+    return hipGetLastError();
+}
 
 int32_t ubqp_screen_blocks(int64_t M) { return (int32_t)((M + CH - 1) / CH); }
 size_t ubqp_screen_partials_bytes(int64_t M) { return (size_t)ubqp_screen_blocks(M) * 3 * sizeof(int64_t); }

@@ -194,6 +194,13 @@ struct ScreenArgs {          // exact T(lambda) screening
     int32_t nblk;
 };
 
+struct OrdArgs {             // the order in which the ascent takes the passers
+    const int64_t *f;        // objectives before the ascent
+    const int32_t *idx;      // passers, ascending
+    const int64_t *npass;
+    int32_t *oidx;           // out: the passers, lowest objective first (bucketed)
+};
+
 struct AscArgs {             // steepest 1-flip ascent
     const void *qa;          // zero diagonal: int8 or int16 [n_pad][ncol_a]
     int32_t ncol_a;          // columns of the ascent matrix (1024 NB)
@@ -293,6 +300,8 @@ int ubqp_tune_eval_internal(ubqp_ctx *ctx, const ubqp_problem *p, int64_t M, int
 
 int32_t ubqp_screen_blocks(int64_t M);
 size_t ubqp_screen_partials_bytes(int64_t M);
+// One block per instance (args[i] for block i).
+hipError_t ubqp_launch_order_batch(hipStream_t st, const OrdArgs *args, int count);
 ScreenArgs ubqp_screen_args(const int64_t *f, int64_t M, int32_t lam_num, int32_t lam_den, int32_t *idx,
                             int64_t *npass, int64_t *sum_max, void *partials);
 hipError_t ubqp_launch_screen(hipStream_t st, const ScreenArgs &a);
