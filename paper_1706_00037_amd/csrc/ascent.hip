@@ -385,8 +385,9 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
 // and its slot is refilled, instead of idling until the slowest wave of a group.
 // Registers hold the keys and signs of 16 NB columns per lane: NB <= 4 fits four
 // waves per SIMD, NB <= 6 three, NB = 7, 8 two.  (Keeping the signs in LDS to fit
-// a third wave at NB = 7 was measured 40% slower: more waves do not get the rows
-// delivered faster.)
+// a third wave at NB = 7 was measured 40% slower, and fitting NB = 7 into three
+// waves' registers directly, with no spill inside the flip loop, 2.1 times slower:
+// more waves do not get the rows delivered faster.)
 template <int NB> struct AscOcc {
     static constexpr int waves = NB <= 4 ? 4 : NB <= 6 ? 3 : 2;
 };
