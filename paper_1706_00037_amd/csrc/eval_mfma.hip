@@ -252,32 +252,64 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     const int word0 = n0 >> 6;
     if constexpr (EPI == EPI_ROWDOT) {
         const int64_t wgt = plane == 0 ? a.weight0 : 1;
+        // With KC = BN the last K step is the diagonal block [n0, n0 + BN): its staged
+        // X words are this tile's columns and its staged Q block holds q_jj on the
+        // diagonal (kept by the k <= j mask), so both come from LDS.  Nothing is
+        // written to LDS after that step's barrier.
+        constexpr bool LDS_EPI = TRI && KC == BN;
+        const int lastbuf = (nk - 1) & 1;
         int32_t dq[FN];  // this plane's q_jj of the lane's columns
 #pragma unroll
         for (int ni = 0; ni < FN; ni++) {
             const int col = n0 + ni * 32 + r32;
-            dq[ni] = ubqp_ldg1(qp + (int64_t)col * a.n_pad + col);
+            if constexpr (LDS_EPI)
+                dq[ni] = Bs[lastbuf][(ni * 32 + r32) * BPITCH + ni * 32 + r32];
+            else
+                dq[ni] = ubqp_ldg1(qp + (int64_t)col * a.n_pad + col);
         }
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
+            int32_t sv[16];
 #pragma unroll
             for (int e = 0; e < 16; e++) {
-                const int64_t row = m0 + wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int rl = wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int64_t row = m0 + rl;
                 uint64_t xw0 = 0, xw1 = 0;
-                if (row < Mrows) {
+                if constexpr (LDS_EPI) {
+                    xw0 = As[lastbuf][rl * APITCH];
+                    xw1 = As[lastbuf][rl * APITCH + 1];
+                } else if (row < Mrows) {
                     if (word0 < a.W) xw0 = ubqp_ldg8(a.X + row * a.W + word0);
                     if (word0 + 1 < a.W) xw1 = ubqp_ldg8(a.X + row * a.W + word0 + 1);
                 }
+                // bit r32 of each 32-column quarter of the tile
+                const uint32_t xq[4] = {(uint32_t)xw0, (uint32_t)(xw0 >> 32), (uint32_t)xw1, (uint32_t)(xw1 >> 32)};
                 int s = 0;
 #pragma unroll
-                for (int ni = 0; ni < FN; ni++) {
-                    const uint64_t xw = ni < 2 ? xw0 : xw1;
-                    s += ((xw >> (32 * (ni & 1) + r32)) & 1ull) ? 2 * acc[mi][ni][e] - dq[ni] : 0;
+                for (int ni = 0; ni < FN; ni++) s += ((xq[ni] >> r32) & 1u) ? 2 * acc[mi][ni][e] - dq[ni] : 0;
+                sv[e] = s;
+            }
+            // |s| <= 4 (2 * 128 n + 128) < 2^24: the 32-lane sums stay inside int32.
+            // The 16 rows are reduced in lockstep so that the DPP steps of different
+            // rows fill each other's wait states.  Every lane of a quad permutation or
+            // a row rotation has a source lane, so bound_ctrl changes nothing but lets
+            // the old value go unused.
+#pragma unroll
+            for (int e = 0; e < 16; e++) sv[e] += __builtin_amdgcn_update_dpp(0, sv[e], 0xB1, 0xF, 0xF, true);
+#pragma unroll
+            for (int e = 0; e < 16; e++) sv[e] += __builtin_amdgcn_update_dpp(0, sv[e], 0x4E, 0xF, 0xF, true);
+#pragma unroll
+            for (int e = 0; e < 16; e++) sv[e] += __builtin_amdgcn_update_dpp(0, sv[e], 0x124, 0xF, 0xF, true);
+#pragma unroll
+            for (int e = 0; e < 16; e++) sv[e] += __builtin_amdgcn_update_dpp(0, sv[e], 0x128, 0xF, 0xF, true);
+#pragma unroll
+            for (int e = 0; e < 16; e++) sv[e] += __shfl_xor(sv[e], 16);
+            if (r32 == 0) {
+#pragma unroll
+                for (int e = 0; e < 16; e++) {
+                    const int64_t row = m0 + wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                    if (row < Mrows && sv[e] != 0) ubqp_atomic_add_i64(&a.f[row], wgt * (int64_t)sv[e]);
                 }
-                // |s| <= 4 (2 * 128 n + 128) < 2^24: the 32-lane sum stays inside int32
-                s = row16_sum(s);
-                s += __shfl_xor(s, 16);
-                if (r32 == 0 && row < Mrows && s != 0) ubqp_atomic_add_i64(&a.f[row], wgt * (int64_t)s);
             }
         }
     } else if constexpr (EPI == EPI_Y) {
