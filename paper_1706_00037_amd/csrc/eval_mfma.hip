@@ -135,6 +135,16 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
 
     uint64_t aw[KC / 64];
     uint4 br[BCH];
+    // Key epilogue with KC = BN: the X words of this tile's columns pass through the
+    // staging registers at the K step kc = n0 / KC; a copy goes to LDS after the
+    // loop for the epilogue (the same gathered rows, zero where the staging is zero).
+    constexpr bool KEYS_LDS = EPI == EPI_KEYS && KC == BN;
+    uint64_t xt[KC / 64] = {};
+    int32_t dg[FN] = {};  // key epilogue: q_jj of the lane's columns, loaded early
+    if constexpr (EPI == EPI_KEYS) {
+#pragma unroll
+        for (int ni = 0; ni < FN; ni++) dg[ni] = a.diag[n0 + ni * 32 + (tid & 31)];
+    }
     const int nk_full = (a.n_pad + KC - 1) / KC;
     const int nk = TRI ? min(nk_full, (n0 + BN + KC - 1) / KC) : nk_full;
     // global -> registers for K step kc; columns past n_pad (the tail of the last step) read as 0
@@ -143,6 +153,9 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
         _Pragma("unroll") for (int w_ = 0; w_ < KC / 64; w_++) {                              \
             const int wi_ = (kc) * (KC / 64) + w_;                                            \
             aw[w_] = (xrow && wi_ < a.W) ? ubqp_ldg8(xrow + wi_) : 0ull;                      \
+        }                                                                                     \
+        if (KEYS_LDS && (kc) * KC == n0) {                                                    \
+            _Pragma("unroll") for (int w_ = 0; w_ < KC / 64; w_++) xt[w_] = aw[w_];           \
         }                                                                                     \
         const bool kin_ = (kc) * KC + bc16 * 16 < a.n_pad;                                    \
         _Pragma("unroll") for (int i_ = 0; i_ < BCH; i_++) {                                  \
@@ -328,28 +341,42 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     } else {
         // Ascent keys of the single-plane problem: with y = (x Q)_j and s = 1 - 2 x_j,
         // Delta_j = q_jj + 2 s y_j, key_j = Delta_j * 256 + 2 (127 - j mod PL) + x_j.
-        int32_t dg[FN];
+        __shared__ uint64_t Xt[KEYS_LDS ? BM * (KC / 64) : 1];
+        // the key's tie-break part 2 (127 - local index in the ascent lane) per column
+        int32_t tb[FN];
 #pragma unroll
-        for (int ni = 0; ni < FN; ni++) dg[ni] = a.diag[n0 + ni * 32 + r32];
+        for (int ni = 0; ni < FN; ni++) tb[ni] = 2 * (127 - (n0 + ni * 32 + r32) % a.keys_pl);
+        if constexpr (KEYS_LDS) {
+#pragma unroll
+            for (int w = 0; w < KC / 64; w++) Xt[tid * (KC / 64) + w] = xt[w];
+            __syncthreads();
+        }
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
 #pragma unroll
             for (int e = 0; e < 16; e++) {
-                const int64_t row = m0 + wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int rl = wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int64_t row = m0 + rl;
                 if (row < Mrows) {
-                    const int64_t xr = a.rows[row];
-                    const bool ok = xr >= 0 && xr < a.x_rows;
-                    const uint64_t xw0 = (ok && word0 < a.W) ? a.X[xr * a.W + word0] : 0ull;
-                    const uint64_t xw1 = (ok && word0 + 1 < a.W) ? a.X[xr * a.W + word0 + 1] : 0ull;
+                    uint64_t xw0 = 0, xw1 = 0;
+                    if constexpr (KEYS_LDS) {
+                        xw0 = Xt[rl * 2];
+                        xw1 = Xt[rl * 2 + 1];
+                    } else {
+                        const int64_t xr = a.rows[row];
+                        const bool ok = xr >= 0 && xr < a.x_rows;
+                        xw0 = (ok && word0 < a.W) ? a.X[xr * a.W + word0] : 0ull;
+                        xw1 = (ok && word0 + 1 < a.W) ? a.X[xr * a.W + word0 + 1] : 0ull;
+                    }
+                    const uint32_t xq[4] = {(uint32_t)xw0, (uint32_t)(xw0 >> 32), (uint32_t)xw1,
+                                            (uint32_t)(xw1 >> 32)};
 #pragma unroll
                     for (int ni = 0; ni < FN; ni++) {
                         const int col = n0 + ni * 32 + r32;
-                        const uint64_t xw = ni < 2 ? xw0 : xw1;
-                        const int32_t xj = (int32_t)((xw >> (32 * (ni & 1) + r32)) & 1ull);
+                        const int32_t xj = (int32_t)((xq[ni] >> r32) & 1u);
                         const int32_t y2 = 2 * acc[mi][ni][e];
                         const int32_t delta = dg[ni] + (xj ? -y2 : y2);
-                        // local index of column col within its ascent lane: col mod PL
-                        a.Y[row * a.n_pad + col] = delta * 256 + 2 * (127 - col % a.keys_pl) + xj;
+                        a.Y[row * a.n_pad + col] = delta * 256 + tb[ni] + xj;
                     }
                 }
             }
