@@ -211,6 +211,9 @@ ASCENT_CASES = [
     (7000, 4, 2, 0.5, -32768, 32767, 0),
     (8192, 3, 1, 0.2, -32768, 32767, 0),  # the largest n
     (5000, 40, 4, 0.05, -3, 3, 0),        # sparse, small values: long ascents with ties
+    (6000, 8, 2, 0.3, -100, 100, 0),      # one plane, six blocks: two waves per candidate
+    (4500, 12, 3, 0.6, -4, 4, 0),         # two waves per candidate, many ties across the waves
+    (7000, 6, 2, 0.5, -100, 100, 9),      # two waves per candidate, capped
 ]
 
 
