@@ -150,6 +150,7 @@ __global__ __launch_bounds__(THR) void screen_scatter_b(const ScreenArgs *args, 
 // changes; every candidate's result is the same in any order.
 constexpr int ORD_THR = 1024;
 constexpr int ORD_BUCKETS = 1024;
+static_assert(ORD_THR == ORD_BUCKETS, "one bucket per thread: zeroing and the scan assume it");
 
 __global__ __launch_bounds__(ORD_THR) void order_batched(const OrdArgs *args, int count)
 {
