@@ -515,7 +515,10 @@ def main():
                     algorithmic="n bytes of Q per flip x flips of the generation",
                     algorithmic_gb_per_launch=byts / 1e9, avg_launch_ms=t_ms,
                     phase_ms_with_delta_init=phase_mean[dom], flips_per_s=flips_mean / (t_ms * 1e-3),
-                    valu_tops=alu, valu_frac=alu / VALU_INT32_TOPS)
+                    valu_tops=alu, valu_frac=alu / VALU_INT32_TOPS,
+                    note="achieved counts every row a flip reads; L2 serves most of them (traffic beyond L2 "
+                         "is the counters' figure), so frac can exceed 1 against HBM; the per-wave flip chain "
+                         "(row read, then the column update) at two waves per SIMD is the limit")
 
     # ---- the paper's Table 1 replica: 1000 random solutions --------------------------
     e1_rep = {}
