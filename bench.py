@@ -97,13 +97,36 @@ def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
     F = float(fl.sum())
     t_flip = max(0.0, t_asc * threads - threads * t_init) / max(F, 1.0)
     t_gen = (M * t_eval + P_per_gen * t_init + flips_per_gen * t_flip) / threads
+    # the oracle's evaluation rate at the three single-instance shapes, one thread and
+    # all `threads` (bounded samples: 8 and 8 * threads candidates)
+    from paper_1706_00037_amd.inputs import CONFIGS, make_instance
+    rates = {}
+    for name in ("cfg1", "cfg2", "cfg3"):
+        c = CONFIGS[name]
+        Qc = Q if c["n"] == n else make_instance(c["n"], c["density"], c["lo"], c["hi"], c["inst_seed"])
+        r = {}
+        for th, cnt in ((1, 8), (threads, 8 * threads)):
+            Xc = random_candidates(cnt, c["n"], 97)
+            t = time.perf_counter()
+            oracle.eval_many(Qc, Xc, threads=th)
+            r[str(th)] = cnt / (time.perf_counter() - t)
+        rates[f"n={c['n']}"] = {"threads": r}
+    host = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                host = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=M / t_gen, unit="evals/s", cores=threads, kind="oracle",
                 sample=f"oracle at n={n}: objective of {Ne} candidates, one delta initialisation and {threads} "
                        f"ascents from random candidates ({int(F)} flips), on {threads} threads; generation time "
                        f"(M t_eval + P t_init + F t_flip)/threads with the timed generations' mean "
                        f"P={P_per_gen:.0f}, F={flips_per_gen:.0f}",
                 ms_per_step=t_gen * 1e3, eval_only_evals_per_s=threads / t_eval,
-                t_eval_ms=t_eval * 1e3, t_init_ms=t_init * 1e3, t_flip_us=t_flip * 1e6)
+                t_eval_ms=t_eval * 1e3, t_init_ms=t_init * 1e3, t_flip_us=t_flip * 1e6,
+                eval_rates_evals_per_s=rates, host_cpu=host, host_logical_cpus=os.cpu_count())
 
 
 def make_request_instance(torch, n, density, seed):
