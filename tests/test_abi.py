@@ -79,3 +79,15 @@ def test_request_footprint_host_logic():
         assert f2 >= 2 * n_pad * n_pad + 2 * n_pad * ncol + 2 * 4096 * n_pad * 4
     assert fp(2000, 1, dict(base, M=8192)) > fp(2000, 1, base)
     assert fp(2000, 1, dict(base, G=100)) > fp(2000, 1, base)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
