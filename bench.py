@@ -391,7 +391,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU design is described in DESIGN.md).", file=sys.stderr)
+              f"(the path is built and measured on one GPU; how it would shard is a design only).",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
