@@ -99,10 +99,10 @@ def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
     t_gen = (M * t_eval + P_per_gen * t_init + flips_per_gen * t_flip) / threads
     # the oracle's evaluation rate at the three single-instance shapes, one thread and
     # all `threads` (bounded samples: 8 and 8 * threads candidates)
-    from paper_1706_00037_amd.inputs import CONFIGS, make_instance
+    from paper_1706_00037_amd.inputs import WORKLOADS, make_instance
     rates = {}
-    for name in ("cfg1", "cfg2", "cfg3"):
-        c = CONFIGS[name]
+    for name in ("n500_d0.10_M1000", "n2500_d0.10_M65536", "n7000_d0.50_M16384"):
+        c = WORKLOADS[name]
         Qc = Q if c["n"] == n else make_instance(c["n"], c["density"], c["lo"], c["hi"], c["inst_seed"])
         r = {}
         for th, cnt in ((1, 8), (threads, 8 * threads)):
@@ -314,13 +314,13 @@ def batched_bench(ctx, ubqp, torch, count=64, G=6, warm=2, seed=4):
                          "(hi/lo int8 planes), M=4096, H=10, lambda=1/2")
 
 
-def sequential_bench(ctx, CONFIGS, make_instance, prob7000, Q7000, c7000):
+def sequential_bench(ctx, WORKLOADS, make_instance, prob7000, Q7000, c7000):
     """The main loop of Fig. 2 as printed, 2500 iterations and Mean over 1000 random
     solutions, on the paper's two instance shapes: n=2500 at density 0.1 (ORLIB)
     and n=7000 at density 0.5 (Palubeckis p7000).  Reports the whole loop's time,
     iterations per second and the time of each replacement of the incumbent."""
     out = {}
-    c2 = CONFIGS["cfg2"]
+    c2 = WORKLOADS["n2500_d0.10_M65536"]
     shapes = [("n2500_d0.1", make_instance(c2["n"], c2["density"], c2["lo"], c2["hi"], c2["inst_seed"]), None,
                c2["run_seed"]),
               ("n7000_d0.5", Q7000, prob7000, c7000["run_seed"])]
@@ -397,7 +397,7 @@ def main():
     import torch
 
     from paper_1706_00037_amd import ubqp
-    from paper_1706_00037_amd.inputs import CONFIGS, make_instance, random_candidates
+    from paper_1706_00037_amd.inputs import WORKLOADS, make_instance, random_candidates
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calib_copy:
@@ -407,7 +407,7 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copy: 1 GiB read, 1 GiB written")
         del src, dst
-    c = CONFIGS["cfg3"]
+    c = WORKLOADS["n7000_d0.50_M16384"]
     n, M, H = c["n"], c["M"], c["H"]
     lam_num, lam_den = (int(t) for t in args.lam.split("/"))
     K, Wm = args.steps, args.warmup
@@ -485,7 +485,7 @@ def main():
     # ---- the paper's own loop: one candidate per iteration (Fig. 2) ------------------
     seq = None
     if not args.no_seq:
-        seq = sequential_bench(ctx, CONFIGS, make_instance, prob, Q, c)
+        seq = sequential_bench(ctx, WORKLOADS, make_instance, prob, Q, c)
 
     # ---- path relinking of an elite set at the headline size -------------------------
     relink = None

@@ -69,11 +69,11 @@ def random_candidates(M: int, n: int, seed: int, p_one: float = 0.5) -> np.ndarr
 
 
 # The workloads (instance seed, run seed and shapes) used by tests and bench.
-CONFIGS = {
-    "cfg1": dict(n=500, density=0.10, lo=-100, hi=100, inst_seed=1001, run_seed=1,
-                 M=1000, H=10, lam=(1, 2), G=20),
-    "cfg2": dict(n=2500, density=0.10, lo=-100, hi=100, inst_seed=2001, run_seed=2,
-                 M=65536, H=10, lam=(1, 2), G=20),
-    "cfg3": dict(n=7000, density=0.50, lo=-100, hi=100, inst_seed=3001, run_seed=3,
-                 M=16384, H=10, lam=(1, 2), G=20),
+WORKLOADS = {
+    "n500_d0.10_M1000": dict(n=500, density=0.10, lo=-100, hi=100, inst_seed=1001, run_seed=1,
+                             M=1000, H=10, lam=(1, 2), G=20),
+    "n2500_d0.10_M65536": dict(n=2500, density=0.10, lo=-100, hi=100, inst_seed=2001, run_seed=2,
+                               M=65536, H=10, lam=(1, 2), G=20),
+    "n7000_d0.50_M16384": dict(n=7000, density=0.50, lo=-100, hi=100, inst_seed=3001, run_seed=3,
+                               M=16384, H=10, lam=(1, 2), G=20),
 }

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1706_00037_amd.inputs import CONFIGS, make_instance, random_candidates
+from paper_1706_00037_amd.inputs import WORKLOADS, make_instance, random_candidates
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -178,7 +178,7 @@ def test_multistart_blend_full_size_sampled(ctx, ub):
     generation-0 candidates rebuilt by the oracle from the random seeds and their
     objectives compared on a sample; each generation's screen statistics
     recomputed from the dumped objectives; the incumbent checked."""
-    c = CONFIGS["cfg3"]
+    c = WORKLOADS["n7000_d0.50_M16384"]
     n, M, H, G = c["n"], c["M"], c["H"], 2
     lam = tuple(c["lam"])
     Q = make_instance(n, c["density"], c["lo"], c["hi"], c["inst_seed"])

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1706_00037_amd.inputs import CONFIGS, make_instance, random_candidates, unpack_bits
+from paper_1706_00037_amd.inputs import WORKLOADS, make_instance, random_candidates, unpack_bits
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -121,7 +121,7 @@ def test_eval_extremes_beyond_int32(ctx, n, v):
 
 def test_eval_full_size_sampled(ctx):
     """7000 variables, 50% density, 16384 candidates: sampled rows against the oracle."""
-    c = CONFIGS["cfg3"]
+    c = WORKLOADS["n7000_d0.50_M16384"]
     n, M = c["n"], c["M"]
     Q = make_instance(n, c["density"], c["lo"], c["hi"], c["inst_seed"])
     X = random_candidates(M, n, 31)
@@ -284,7 +284,7 @@ def _compare_multistart(ctx, Q, **kw):
 
 def test_multistart_config1_full(ctx):
     """500 variables, 10% density, 1000 candidates per generation, 20 generations."""
-    c = CONFIGS["cfg1"]
+    c = WORKLOADS["n500_d0.10_M1000"]
     Q = make_instance(c["n"], c["density"], c["lo"], c["hi"], c["inst_seed"])
     _compare_multistart(ctx, Q, M=c["M"], H=c["H"], lam_num=c["lam"][0], lam_den=c["lam"][1], G=c["G"],
                         run_seed=c["run_seed"])
@@ -308,14 +308,14 @@ def test_multistart_matches_oracle(ctx, case):
         assert not r["have_best"]
 
 
-@pytest.mark.parametrize("cfg", ["cfg2", "cfg3"])
-def test_multistart_full_size_sampled(ctx, cfg):
+@pytest.mark.parametrize("workload", ["n2500_d0.10_M65536", "n7000_d0.50_M16384"])
+def test_multistart_full_size_sampled(ctx, workload):
     """The bench's launch configuration at full size (n=2500, M=65536 and n=7000,
     M=16384), two generations: generation-0 candidates rebuilt by the oracle one by
     one and their objectives compared; every generation's screen statistics
     recomputed by the oracle from the dumped objectives; the incumbent's value and
     1-flip local optimality checked against the oracle."""
-    c = CONFIGS[cfg]
+    c = WORKLOADS[workload]
     n, M, H, G = c["n"], c["M"], c["H"], 2
     lam = tuple(c["lam"])
     Q = make_instance(n, c["density"], c["lo"], c["hi"], c["inst_seed"])

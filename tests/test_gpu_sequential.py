@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1706_00037_amd.inputs import CONFIGS, make_instance, unpack_bits
+from paper_1706_00037_amd.inputs import WORKLOADS, make_instance, unpack_bits
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -107,7 +107,7 @@ def test_time_budget_stops_early_on_a_prefix(ctx):
 def test_full_size_orlib_shape_matches_oracle(ctx):
     """n=2500, density 0.1, 2500 iterations: the shape of the paper's ORLIB runs,
     compared whole with the oracle."""
-    c = CONFIGS["cfg2"]
+    c = WORKLOADS["n2500_d0.10_M65536"]
     n = c["n"]
     Q = make_instance(n, c["density"], c["lo"], c["hi"], c["inst_seed"])
     kw = dict(iterations=2500, samples=1000, lam_num=1, lam_den=2, run_seed=c["run_seed"])
