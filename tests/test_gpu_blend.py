@@ -203,3 +203,12 @@ def test_unknown_flags_rejected(ctx, ub):
     prob = ctx.problem(make_instance(50, 0.5, -100, 100, 1))
     with pytest.raises(ub.UbqpError):
         ctx.multistart(prob, M=20, H=2, lam_num=1, lam_den=2, G=1, flags=1 << 10)
+
+
+def test_blend_single_candidate(ctx):
+    n = 200
+    seeds = random_candidates(3, n, 12)
+    Xd = torch.full((1, (n + 63) // 64), -1, dtype=torch.int64, device="cuda")
+    ctx.blend(n, dev(seeds), Xd, 5, 21)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u64(Xd), oracle.blend(n, seeds, 1, 5, 21))

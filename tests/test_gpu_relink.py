@@ -92,3 +92,21 @@ def test_relink_rejects_bad_arguments(ctx, ub):
     with pytest.raises(ub.UbqpError):
         ctx.sync()
     ctx.sync()
+
+
+def test_relink_single_pair_of_identical_rows(ctx):
+    """A pair whose two solutions coincide: no intermediate, the row unchanged."""
+    n = 90
+    Q = make_instance(n, 0.5, -100, 100, 3)
+    elite = random_candidates(1, n, 4)
+    prob = ctx.problem(Q)
+    ed = torch.from_numpy(elite.view(np.int64)).cuda()
+    pairs = torch.tensor([[0, 0]], dtype=torch.int32, device="cuda")
+    X = torch.full((1, prob.W), -1, dtype=torch.int64, device="cuda")
+    fm = torch.zeros(1, dtype=torch.int64, device="cuda")
+    fo = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    ctx.relink(prob, ed, pairs, X, fm, fo, st)
+    ctx.sync()
+    assert st.item() == 0 and fm.item() == np.iinfo(np.int64).min and fo.item() == fm.item()
+    assert np.array_equal(X.cpu().numpy().view(np.uint64), elite)

@@ -124,3 +124,17 @@ def test_bad_parameters_rejected(ctx, ub):
                 dict(flags=ub.UBQP_BLEND), dict(time_budget_ms=-1.0), dict(max_flips=-1)):
         with pytest.raises(ub.UbqpError):
             ctx.sequential(prob, **dict(good, **bad))
+
+
+@pytest.mark.parametrize("I,Ms,batch", [(1, 1, 1), (2, 1, 1), (3, 2, 2), (40, 5, 1)])
+def test_degenerate_shapes(ctx, I, Ms, batch):
+    """One iteration (the starting solution alone), a single sample, the smallest
+    window."""
+    n = 70
+    Q = make_instance(n, 0.5, -100, 100, 71)
+    kw = dict(iterations=I, samples=Ms, lam_num=1, lam_den=2, run_seed=9)
+    o = oracle.sequential(Q, H=n, threads=2, **kw)
+    dump = torch.zeros(I, dtype=torch.int64, device="cuda")
+    r = ctx.sequential(ctx.problem(Q), H=0, batch=batch, f_dump=dump, **kw)
+    _same(r, o, (I, Ms, batch))
+    assert np.array_equal(dump.cpu().numpy(), o["f_dump"])
