@@ -309,7 +309,7 @@ typedef struct {
     int32_t lam_num;        /* lambda = lam_num / lam_den, 0 <= lam_num <= lam_den              */
     int32_t lam_den;
     int32_t max_flips;      /* flips per ascent, 0 = until a 1-flip local optimum             */
-    int32_t batch;          /* largest window, 1..UBQP_SEQ_MAX_BATCH, 0 = 4096 (speed only)    */
+    int32_t batch;          /* largest window, 1..UBQP_SEQ_MAX_BATCH, 0 = 1024 (speed only)    */
     uint32_t flags;         /* UBQP_NO_GRAPH, or 0                                             */
     int32_t pad_;
     uint64_t run_seed;      /* SplitMix64 seed of the samples                                  */
