@@ -73,15 +73,15 @@ def parse():
 
 def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
     """The oracle as it stands, on the host cores, timed on a bounded sample of the
-    workload.  Measured: the objective of 32*threads candidates (threads in
+    workload.  Measured: the objective of 96*threads candidates (threads in
     parallel), one closed-form delta vector (the ascent's initialisation) and
-    `threads` full ascents from random candidates (threads in parallel).  A
+    2*threads full ascents from random candidates (threads in parallel).  A
     generation then costs (M t_eval + P t_init + F t_flip) / threads of wall time
     with the timed generations' own passer count P and flip count F."""
     import oracle
     from paper_1706_00037_amd.inputs import random_candidates
 
-    Ne = 32 * threads
+    Ne = 96 * threads
     Xs = random_candidates(Ne, n, 99)
     t = time.perf_counter()
     oracle.eval_many(Q, Xs, threads=threads)
@@ -89,13 +89,14 @@ def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
     t = time.perf_counter()
     oracle.delta(Q, Xs[0])
     t_init = time.perf_counter() - t                              # serial seconds per initialisation
-    Xa = random_candidates(threads, n, 98)
+    Na = 2 * threads
+    Xa = random_candidates(Na, n, 98)
     fa = oracle.eval_many(Q, Xa, threads=threads)
     t = time.perf_counter()
-    _, _, fl = oracle.ascent_many(Q, Xa, np.arange(threads, dtype=np.int32), fa, threads=threads)
+    _, _, fl = oracle.ascent_many(Q, Xa, np.arange(Na, dtype=np.int32), fa, threads=threads)
     t_asc = time.perf_counter() - t
     F = float(fl.sum())
-    t_flip = max(0.0, t_asc * threads - threads * t_init) / max(F, 1.0)
+    t_flip = max(0.0, t_asc * threads - Na * t_init) / max(F, 1.0)
     t_gen = (M * t_eval + P_per_gen * t_init + flips_per_gen * t_flip) / threads
     # the oracle's evaluation rate at the three single-instance shapes, one thread and
     # all `threads` (bounded samples: 8 and 8 * threads candidates)
@@ -120,7 +121,7 @@ def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
     except OSError:
         pass
     return dict(value=M / t_gen, unit="evals/s", cores=threads, kind="oracle",
-                sample=f"oracle at n={n}: objective of {Ne} candidates, one delta initialisation and {threads} "
+                sample=f"oracle at n={n}: objective of {Ne} candidates, one delta initialisation and {Na} "
                        f"ascents from random candidates ({int(F)} flips), on {threads} threads; generation time "
                        f"(M t_eval + P t_init + F t_flip)/threads with the timed generations' mean "
                        f"P={P_per_gen:.0f}, F={flips_per_gen:.0f}",
