@@ -63,7 +63,8 @@ def parse():
     ap.add_argument("--no-blend", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--no-relink", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-active", type=int, default=32)
     ap.add_argument("--calib-copy", action="store_true",
@@ -579,7 +580,7 @@ def main():
     # ---- serving: Poisson arrivals against the request server -------------------------
     serving = None
     if not args.no_serve:
-        serving = serving_bench(ctx, ubqp, torch, R=args.serve_requests, rate=args.serve_rate,
+        serving = serving_bench(ctx, ubqp, torch, R=args.serve_requests, warm=args.serve_warmup, rate=args.serve_rate,
                                 max_active=args.serve_active)
 
     # ---- CPU oracle -----------------------------------------------------------------
