@@ -31,6 +31,13 @@
 
 namespace {
 
+// s_waitcnt vmcnt(0) lgkmcnt(0) (expcnt left at its maximum), as the builtin's
+// immediate.  Issued before a flip loop: flat accesses still in flight there
+// (argument tables, the previous candidate's results) would otherwise make the
+// compiler wait for every load in flight at each flip instead of for the row
+// block it needs.
+constexpr unsigned WAIT_VM_LGKM_0 = 0x0070;
+
 
 typedef int32_t v16i __attribute__((ext_vector_type(16)));
 
@@ -133,10 +140,14 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
     }
 
     const int8_t *qa = (const int8_t *)a.qa;
-    int64_t fv = a.f[c];
+    // the gain is summed from zero and f read only after the loop: a load still in
+    // flight at the loop's first use (f is read through a flat pointer) would put a
+    // wait on all memory into every flip
+    int64_t gain = 0;
     int32_t flips = 0;
     const int32_t cap = a.max_flips > 0 ? a.max_flips : a.safety_cap;
     int32_t V;
+    __builtin_amdgcn_s_waitcnt(WAIT_VM_LGKM_0);
     for (;;) {
         int32_t bmax[NB];
 #pragma unroll
@@ -168,7 +179,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
                 for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts >> 2)) ? sflip : 0u;
             }
         }
-        fv += V;
+        gain += V;
         flips++;
         // Delta_i += 2 d s_i q_ik for i != k, with d = 1 - 2 x_k: key_i += (q_ik s_i) * 512 d
         const int32_t step = xk ? -512 : 512;
@@ -199,7 +210,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         if (ci < 4 * a.W) ((uint16_t *)xr)[ci] = (uint16_t)bits;
     }
     if (lane == 0) {
-        a.f[c] = fv;
+        a.f[c] += gain;
         a.flips[c] = flips;
     }
 }
@@ -294,10 +305,14 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
     }
 
     const int16_t *qa = (const int16_t *)a.qa;
-    int64_t fv = a.f[c];
+    // the gain is summed from zero and f read only after the loop: a load still in
+    // flight at the loop's first use (f is read through a flat pointer) would put a
+    // wait on all memory into every flip
+    int64_t gain = 0;
     int32_t flips = 0;
     const int32_t cap = a.max_flips > 0 ? a.max_flips : a.safety_cap;
     int32_t V;
+    __builtin_amdgcn_s_waitcnt(WAIT_VM_LGKM_0);
     for (;;) {
         int32_t bm[NB];
 #pragma unroll
@@ -341,7 +356,7 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
                 for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts >> 2)) ? sflip : 0u;
             }
         }
-        fv += V;
+        gain += V;
         flips++;
         // Delta_i += 2 d s_i q_ik for i != k, d = 1 - 2 x_k (the ascent matrix has q_kk = 0)
         const int32_t step = xk ? -2 : 2;
@@ -376,7 +391,7 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
         if (ci < 4 * a.W) ((uint16_t *)xr)[ci] = (uint16_t)bits;
     }
     if (lane == 0) {
-        a.f[c] = fv;
+        a.f[c] += gain;
         a.flips[c] = flips;
     }
 }
@@ -526,6 +541,7 @@ __device__ void relink_path(const RelArgs &a, int64_t p, int lane)
         for (int r = 0; r < 4; r++) sb[b][r] = ss[b][r];
     int64_t fv = a.f0[p], best = INT64_MIN;
     int32_t bstep = 0;
+    __builtin_amdgcn_s_waitcnt(WAIT_VM_LGKM_0);
     for (int s = 1; s < nd; s++) {
         int32_t bm[NB];
 #pragma unroll
