@@ -430,6 +430,28 @@ UBQP_API int ubqp_server_stats(ubqp_server *server, int64_t out[8]);
 UBQP_API const char *ubqp_server_error(ubqp_server *server);
 UBQP_API int ubqp_server_destroy(ubqp_server *server);
 
+/*
+ * Benchmark files (Computational results section: the OR-Library bqp sets and
+ * the Palubeckis instances are the paper's test problems).  Host code only: no
+ * context and no device are needed.  Both formats are whitespace-separated
+ * integers whose entries are 1-based (i, j, q) triples; each listed value fills
+ * q_ij and q_ji (so an off-diagonal pair adds 2 q x_i x_j to f = x'Qx); a pair
+ * listed twice must carry the same value both times (else UBQP_EASYM).
+ */
+#define UBQP_FMT_ORLIB 1    /* K, then K problems, each: n, nnz, nnz triples          */
+#define UBQP_FMT_TRIPLETS 2 /* one problem: n, nnz, nnz triples                       */
+
+/* Read problem `index` (0-based) of the file at `path`.  *count_out receives the
+ * number of problems in the file and *n_out that problem's n.  With q_host NULL
+ * only these two are returned (a size query); otherwise q_host (q_cap >= n * n
+ * int32, caller-owned) receives the dense row-major matrix, zero where no entry
+ * is listed, ready for ubqp_problem_create.  Returns UBQP_OK, UBQP_EINVAL (null
+ * argument, unknown format, unreadable or malformed file, index out of range,
+ * q_cap too small), UBQP_ERANGE (n > UBQP_MAX_N or a value outside int32) or
+ * UBQP_EASYM; err (err_len bytes, may be NULL) receives the reason. */
+UBQP_API int ubqp_read_instance(const char *path, int32_t format, int32_t index, int32_t *count_out,
+                                int32_t *n_out, int32_t *q_host, int64_t q_cap, char *err, int32_t err_len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "ubqp.h")
 UBQP_OK, UBQP_EINVAL, UBQP_ERANGE, UBQP_EASYM, UBQP_ENOMEM, UBQP_EDEVICE = 0, -1, -2, -3, -4, -5
 UBQP_DERIV_START, UBQP_TIMING, UBQP_NO_GRAPH, UBQP_AUTOTUNE, UBQP_BLEND = 1, 2, 4, 8, 16
 UBQP_EVAL_VARIANTS = 6
+UBQP_FMT_ORLIB, UBQP_FMT_TRIPLETS = 1, 2
 PHASES = ("diversify", "eval", "screen", "ascent", "select", "ascent_kernel")  # the last is a part of "ascent"
 MAX_N, MAX_M, MAX_H = 8192, 1 << 22, 256
 INT64_MIN = -(1 << 63)
@@ -113,6 +114,7 @@ def load():
         "ubqp_server_wait": [P, i64, P, i32, ctypes.POINTER(i32)],
         "ubqp_server_stats": [P, P],
         "ubqp_server_destroy": [P],
+        "ubqp_read_instance": [ctypes.c_char_p, i32, i32, P, P, P, i64, P, i32],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -130,6 +132,35 @@ def load():
     L.ubqp_server_error.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+def read_instance(path: str, fmt: int = UBQP_FMT_ORLIB, index: int = 0):
+    """Problem `index` of a benchmark file (ubqp_read_instance): returns
+    (dense symmetric int32 numpy matrix, number of problems in the file)."""
+    L = load()
+    err = ctypes.create_string_buffer(512)
+    count, n = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = L.ubqp_read_instance(os.fsencode(path), fmt, index, ctypes.byref(count), ctypes.byref(n), None, 0,
+                              err, len(err))
+    if rc != UBQP_OK:
+        raise UbqpError(rc, err.value.decode())
+    Q = np.zeros((n.value, n.value), dtype=np.int32)
+    rc = L.ubqp_read_instance(os.fsencode(path), fmt, index, ctypes.byref(count), ctypes.byref(n),
+                              Q.ctypes.data_as(ctypes.c_void_p), Q.size, err, len(err))
+    if rc != UBQP_OK:
+        raise UbqpError(rc, err.value.decode())
+    return Q, count.value
+
+
+def time_to_target(result: dict, target: int):
+    """First generation whose incumbent reaches `target` in a run's result (its
+    stats and gen_ms): (generation, ms from the start of the run to the end of
+    that generation), or None when no generation reaches it."""
+    stats, gen_ms = result["stats"], result["gen_ms"]
+    for g in range(int(result["generations"])):
+        if int(stats[g][4]) >= target:
+            return g, float(gen_ms[g])
+    return None
 
 
 def _words(n: int) -> int:
