@@ -37,6 +37,7 @@ METRIC = "exact xQx evals/s at n=7000 (vs plain); served solves/s + p50/p99 late
 HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0      # dense int8 matrix-core peak, TOP/s
 VALU_INT32_TOPS = 39.3       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, int32 ops/s / 1e12
+L2_PEAK_GBS = 39322.0        # 8 XCD x 16 L2 channels x 128 B/clock x 2.4 GHz (derived, read side)
 PAPER_TABLE1_S = {2500: 0.7, 5000: 2.0, 6000: 3.0, 7000: 3.5}   # GPU seconds per 1000 evals
 # Memory traffic per launch of the two main kernels at this workload, from the two
 # counter passes summarised in profiles/counters_n7000_M16384.md (FETCH_SIZE and
@@ -542,6 +543,7 @@ def main():
                     algorithmic_gb_per_launch=byts / 1e9, avg_launch_ms=t_ms,
                     phase_ms_with_delta_init=phase_mean[dom], flips_per_s=flips_mean / (t_ms * 1e-3),
                     valu_tops=alu, valu_frac=alu / VALU_INT32_TOPS,
+                    l2_peak_gbs_derived=L2_PEAK_GBS, frac_l2=ach / L2_PEAK_GBS,
                     note="achieved counts every row a flip reads; L2 serves most of them (traffic beyond L2 "
                          "is the counters' figure), so frac can exceed 1 against HBM; the per-wave flip chain "
                          "(row read, then the column update) at two waves per SIMD is the limit")
