@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--lam", default="1/2")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-lam-sweep", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-blend", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
@@ -464,6 +465,36 @@ def main():
             log(f"[bench] lambda {ln}/{ld}: {tl:.3f} ms/generation, P={stl[:, 2].mean():.0f} "
                 f"flips={stl[:, 3].mean():.0f}")
 
+    # ---- the small and the timing-table configurations end to end ------------------------
+    # n=500 (M=1000) and n=2500 (M=65536), 20 generations each from generation 0, with
+    # the mean phase times of the generations after the first
+    configs = {}
+    if not args.no_configs:
+        for name in ("n500_d0.10_M1000", "n2500_d0.10_M65536"):
+            cc = WORKLOADS[name]
+            Qc = make_instance(cc["n"], cc["density"], cc["lo"], cc["hi"], cc["inst_seed"])
+            pc = ctx.problem(Qc)
+            kw = dict(M=cc["M"], H=cc["H"], lam_num=cc["lam"][0], lam_den=cc["lam"][1], G=cc["G"],
+                      run_seed=cc["run_seed"], flags=ubqp.UBQP_TIMING)
+            ctx.multistart(pc, **dict(kw, G=2))   # warm-up (graph capture, workspaces)
+            torch.cuda.synchronize()
+            tc0 = time.perf_counter()
+            rc = ctx.multistart(pc, **kw)
+            torch.cuda.synchronize()
+            tc = (time.perf_counter() - tc0) * 1e3
+            stc = rc["stats"]
+            configs[name] = dict(n=cc["n"], M=cc["M"], G=cc["G"], ms_total_call=tc,
+                                 ms_total_events=float(rc["gen_ms"][-1]),
+                                 ms_per_generation=float(rc["gen_ms"][-1]) / cc["G"],
+                                 evals_per_s=cc["M"] * cc["G"] / (tc * 1e-3), best_f=rc["best_f"],
+                                 passers_per_gen=float(stc[:, 2].mean()), flips_per_gen=float(stc[:, 3].mean()),
+                                 phases_ms_after_gen0={ph: float(rc["phase_ms"][1:, i].mean())
+                                                       for i, ph in enumerate(ubqp.PHASES)})
+            del pc
+            log(f"[bench] {name}: {cc['G']} generations in {tc:.2f} ms ({configs[name]['evals_per_s']:.3g} evals/s), "
+                f"best f {rc['best_f']}, phases after generation 0 "
+                f"{ {k: round(v, 4) for k, v in configs[name]['phases_ms_after_gen0'].items()} }")
+
     # ---- the headline workload with blending diversification -------------------------
     blend = None
     if not args.no_blend:
@@ -625,6 +656,7 @@ def main():
                       "traffic_gb_per_launch": TRAFFIC_GB["eval"]},
         "e1_replica": e1_rep,
         "lambda_sweep": lam_sweep,
+        "configs": configs,
         "blend": blend,
         "sequential": seq,
         "relink": relink,
