@@ -115,6 +115,16 @@ def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
             oracle.eval_many(Qc, Xc, threads=th)
             r[str(th)] = cnt / (time.perf_counter() - t)
         rates[f"n={c['n']}"] = {"threads": r}
+    # the small configuration end to end (n=500, M=1000, 20 generations), whole, one
+    # thread and all threads
+    c1 = WORKLOADS["n500_d0.10_M1000"]
+    Q1 = make_instance(c1["n"], c1["density"], c1["lo"], c1["hi"], c1["inst_seed"])
+    e2e = {}
+    for th in (1, threads):
+        t = time.perf_counter()
+        o1 = oracle.multistart(Q1, M=c1["M"], H=c1["H"], lam_num=c1["lam"][0], lam_den=c1["lam"][1], G=c1["G"],
+                               run_seed=c1["run_seed"], threads=th)
+        e2e[str(th)] = dict(s=time.perf_counter() - t, best_f=o1["best_f"])
     host = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -130,7 +140,8 @@ def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
                        f"P={P_per_gen:.0f}, F={flips_per_gen:.0f}",
                 ms_per_step=t_gen * 1e3, eval_only_evals_per_s=threads / t_eval,
                 t_eval_ms=t_eval * 1e3, t_init_ms=t_init * 1e3, t_flip_us=t_flip * 1e6,
-                eval_rates_evals_per_s=rates, host_cpu=host, host_logical_cpus=os.cpu_count())
+                eval_rates_evals_per_s=rates, e2e_n500_M1000_G20_threads=e2e, host_cpu=host,
+                host_logical_cpus=os.cpu_count())
 
 
 def make_request_instance(torch, n, density, seed):
