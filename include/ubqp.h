@@ -44,6 +44,7 @@ extern "C" {
 #define UBQP_EASYM -3   /* Q is not symmetric                                       */
 #define UBQP_ENOMEM -4  /* device allocation failed                                 */
 #define UBQP_EDEVICE -5 /* a HIP call or a kernel-side check failed (see last_error) */
+#define UBQP_EBUSY -6   /* serving: the waiting queue is at its limit; submit later  */
 
 #define UBQP_MAX_N 8192
 #define UBQP_MAX_M (1ll << 22)
@@ -415,10 +416,16 @@ typedef struct {
 /* Pool bytes a request occupies while admitted (-1 if the arguments are invalid). */
 UBQP_API int64_t ubqp_request_footprint(int32_t n, int32_t elem_bytes, const ubqp_params *params);
 UBQP_API int ubqp_server_create(ubqp_ctx *ctx, int64_t pool_bytes, int32_t max_active, ubqp_server **out);
-/* Errors: UBQP_EINVAL (arguments, or a footprint larger than the whole pool). */
+/* Errors: UBQP_EINVAL (arguments, or a footprint larger than the whole pool),
+ * UBQP_EBUSY (the waiting queue is at the limit set by ubqp_server_set_queue_limit). */
 UBQP_API int ubqp_server_submit(ubqp_server *server, int32_t n, const void *q_host, int32_t elem_bytes,
                                 const ubqp_params *params, uint64_t *best_x_host, int64_t *stats_host,
                                 int64_t *id);
+/* Most requests that may wait for admission at once (0, the default: no limit).
+ * While that many wait, ubqp_server_submit returns UBQP_EBUSY and takes nothing
+ * (backpressure for callers that must not queue without bound).  Errors:
+ * UBQP_EINVAL (null server, max_waiting < 0). */
+UBQP_API int ubqp_server_set_queue_limit(ubqp_server *server, int64_t max_waiting);
 UBQP_API int ubqp_server_wait(ubqp_server *server, int64_t timeout_us, ubqp_request_info *done, int32_t max,
                               int32_t *count);
 /* Counters: {submitted, finished, failed, generations launched, most requests

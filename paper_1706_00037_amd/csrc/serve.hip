@@ -181,6 +181,7 @@ struct ubqp_server {
     std::mutex m;
     std::condition_variable cv_work, cv_done;
     std::deque<Req *> queue;               // guarded by m
+    int64_t queue_limit = 0;               // guarded by m: most requests waiting (0: no limit)
     std::deque<ubqp_request_info> done;    // guarded by m
     bool stop = false;                     // guarded by m
     bool dead = false;                     // guarded by m: a device failure ended the worker
@@ -651,6 +652,11 @@ int ubqp_server_submit(ubqp_server *s, int32_t n, const void *q_host, int32_t el
             delete r;
             return UBQP_EINVAL;
         }
+        if (s->queue_limit > 0 && (int64_t)s->queue.size() >= s->queue_limit) {
+            s->err = "the waiting queue is at its limit";
+            delete r;
+            return UBQP_EBUSY;
+        }
         r->id = s->next_id++;
         *id = r->id;
         s->queue.push_back(r);
@@ -658,6 +664,18 @@ int ubqp_server_submit(ubqp_server *s, int32_t n, const void *q_host, int32_t el
         s->cnt[C_WAITING]++;
     }
     s->cv_work.notify_one();
+    return UBQP_OK;
+}
+
+int ubqp_server_set_queue_limit(ubqp_server *s, int64_t max_waiting)
+{
+    if (!s) return UBQP_EINVAL;
+    if (max_waiting < 0) {
+        set_err(s, "negative queue limit");
+        return UBQP_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(s->m);
+    s->queue_limit = max_waiting;
     return UBQP_OK;
 }
 

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libubqp.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ubqp.h")
 
-UBQP_OK, UBQP_EINVAL, UBQP_ERANGE, UBQP_EASYM, UBQP_ENOMEM, UBQP_EDEVICE = 0, -1, -2, -3, -4, -5
+UBQP_OK, UBQP_EINVAL, UBQP_ERANGE, UBQP_EASYM, UBQP_ENOMEM, UBQP_EDEVICE, UBQP_EBUSY = 0, -1, -2, -3, -4, -5, -6
 UBQP_DERIV_START, UBQP_TIMING, UBQP_NO_GRAPH, UBQP_AUTOTUNE, UBQP_BLEND = 1, 2, 4, 8, 16
 UBQP_EVAL_VARIANTS = 6
 UBQP_FMT_ORLIB, UBQP_FMT_TRIPLETS = 1, 2
@@ -112,6 +112,7 @@ def load():
         "ubqp_server_create": [P, i64, i32, ctypes.POINTER(P)],
         "ubqp_server_submit": [P, i32, P, i32, ctypes.POINTER(Params), P, P, ctypes.POINTER(i64)],
         "ubqp_server_wait": [P, i64, P, i32, ctypes.POINTER(i32)],
+        "ubqp_server_set_queue_limit": [P, i64],
         "ubqp_server_stats": [P, P],
         "ubqp_server_destroy": [P],
         "ubqp_read_instance": [ctypes.c_char_p, i32, i32, P, P, P, i64, P, i32],
@@ -348,6 +349,13 @@ class Server:
             self._err(rc)
         self._live[rid.value] = (Q, bx, st)
         return rid.value
+
+    def set_queue_limit(self, max_waiting: int):
+        """At most max_waiting requests wait for admission (0: no limit); a submit
+        beyond it raises UbqpError with code UBQP_EBUSY."""
+        rc = self.L.ubqp_server_set_queue_limit(self.h, int(max_waiting))
+        if rc != UBQP_OK:
+            self._err(rc)
 
     def wait(self, timeout_s=None, max_items: int = 256) -> list:
         """Finished requests (at least one unless the timeout passes), as dicts."""

@@ -205,3 +205,41 @@ def test_request_errors(ctx, ub):
     assert got[i_wide]["status"] == ub.UBQP_ERANGE
     assert got[i_ok]["status"] == ub.UBQP_OK
     _same(got[i_ok], _alone(ctx, Q, pr), "ok")
+
+
+def test_queue_limit_returns_busy(ctx, ub):
+    """With one slot and at most two requests waiting, a burst of submits behind a
+    long request is refused with UBQP_EBUSY once two wait; the accepted ones equal
+    the solve alone, and submits are taken again once the queue drains."""
+    long_q = make_instance(2000, 0.3, -100, 100, 9400).astype(np.int8)
+    long_pr = dict(M=4096, H=10, lam_num=1, lam_den=2, G=10, max_flips=0, flags=0, run_seed=80)
+    small = [(make_instance(200, 0.5, -100, 100, 9410 + k).astype(np.int8),
+              dict(M=300, H=5, lam_num=1, lam_den=2, G=2, max_flips=0, flags=0, run_seed=90 + k)) for k in range(8)]
+    srv = ub.Server(ctx, pool_bytes=1 << 30, max_active=1)
+    try:
+        with pytest.raises(ub.UbqpError) as e:
+            srv.set_queue_limit(-1)
+        assert e.value.code == ub.UBQP_EINVAL
+        srv.set_queue_limit(2)
+        ids = {srv.submit(long_q, **long_pr): (long_q, long_pr)}
+        busy = 0
+        for Q, pr in small:
+            try:
+                ids[srv.submit(Q, **pr)] = (Q, pr)
+            except ub.UbqpError as err:
+                assert err.code == ub.UBQP_EBUSY
+                busy += 1
+        assert busy >= 1 and len(ids) <= 4, (busy, len(ids))
+        got = _collect(srv, list(ids))
+        Q, pr = small[-1]
+        ids2 = [srv.submit(Q, **pr) for _ in range(2)]           # the queue drained: taken again
+        got.update(_collect(srv, ids2))
+        srv.set_queue_limit(0)                                   # no limit
+        ids3 = [srv.submit(Q, **pr) for _ in range(6)]
+        got.update(_collect(srv, ids3))
+    finally:
+        srv.close()
+    for i, (Q, pr) in ids.items():
+        _same(got[i], _alone(ctx, Q, pr), i)
+    for i in ids2 + ids3:
+        _same(got[i], _alone(ctx, *small[-1]), i)
