@@ -27,7 +27,11 @@
  *                    (greedy relinking, rule read here; orc_relink_path)
  * The readings taken where the paper is silent are listed at each function.
  *
- * Pins that do not come from this file are in tests/test_oracle_*.py.
+ * Pins that do not come from this file are in tests/test_oracle_*.py.  Parity
+ * unpinned: beyond the properties those pins fix (brute force at small n, closed
+ * forms, invariants, sign-definite Q), the full multi-generation trajectories of
+ * orc_multistart, orc_sequential and orc_relink_many at large n are checked by
+ * nothing but this file; the paper prints no per-instance trajectory.
  */
 #include <stdint.h>
 #include <stdlib.h>
