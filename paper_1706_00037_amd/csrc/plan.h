@@ -96,7 +96,7 @@ struct GenTables {
     std::vector<EvalGroup> ev;
     Table<ScreenArgs> scr;
     Table<OrdArgs> ord;                 // one block per instance
-    Table<SelArgs> sel_cand, sel_seed;  // same arguments, two prefixes
+    Table<SelArgs> sel_cand, sel_rank, sel_seed;  // same arguments, three prefixes
     Table<SelArgs> init;                // generation-0 seeds of the joining instances
     std::vector<Chunk> chunks;
     bool has_dump = false;

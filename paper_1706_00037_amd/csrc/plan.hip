@@ -82,6 +82,7 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
                                          r.at<uint64_t>(L.bestx), seeds, r.at<int64_t>(L.stats),
                                          (pr.flags & UBQP_DERIV_START) ? p->deriv_x : nullptr, r.dump);
         sel_cand.add(sl, ubqp_cand_blocks(sl));
+        sel_rank.add(sl, ubqp_rank_blocks(sl));
         sel_seed.add(sl, ubqp_seed_blocks(sl));
         if (!join || (*join)[(size_t)(&r - inst.data())]) init.add(sl, ubqp_seed_blocks(sl));
     }
@@ -132,6 +133,7 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
     scr.stage(host);
     ord.stage(host);
     sel_cand.stage(host);
+    sel_rank.stage(host);
     sel_seed.stage(host);
     init.stage(host);
     for (Chunk &ch : chunks) {
@@ -148,6 +150,7 @@ void GenTables::bind(char *dev)
     scr.bind(dev);
     ord.bind(dev);
     sel_cand.bind(dev);
+    sel_rank.bind(dev);
     sel_seed.bind(dev);
     init.bind(dev);
     for (Chunk &ch : chunks) {
@@ -231,8 +234,8 @@ hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t 
         }
     }
     MARK(4);
-    Q(ubqp_launch_select_batch(st, t.sel_cand.d_args, t.sel_cand.d_pre, t.sel_cand.total(), t.sel_seed.d_pre,
-                               t.sel_seed.total(), n));
+    Q(ubqp_launch_select_batch(st, t.sel_cand.d_args, t.sel_cand.d_pre, t.sel_cand.total(), t.sel_rank.d_pre,
+                               t.sel_rank.total(), t.sel_seed.d_pre, t.sel_seed.total(), n));
     MARK(5);
 #undef MARK
 #undef Q

@@ -17,6 +17,7 @@
 namespace {
 
 constexpr int THR = 256;
+constexpr int RANK_SPLIT = 4;  // ranking blocks per 256 candidates
 
 __device__ inline uint64_t random_word(uint64_t run_seed, int64_t g, int64_t S, int64_t s, int32_t W, int32_t w,
                                        int32_t n)
@@ -100,7 +101,7 @@ __device__ void incumbent_body(const SelArgs &a)
         for (int w = threadIdx.x; w < a.W; w += THR) a.best_x[w] = a.X[(int64_t)winner * a.W + w];
 }
 
-// Rank of each passer by (f desc, index asc): the instance's ceil(M / 256)
+// Rank of each passer by (f desc, index asc): the instance's RANK_SPLIT ceil(M / 256)
 // blocks split into E = ceil(P / 256) passer chunks times as many slices of the
 // comparison range as fit; each block adds its partial counts to rank[] (zeroed
 // by the incumbent kernel).
@@ -110,7 +111,7 @@ __device__ void rank_body(const SelArgs &a, int64_t bid)
     const int64_t P = a.scal->npass;
     const int64_t E = (P + THR - 1) / THR;
     if (E == 0) return;
-    const int64_t nblk = (a.M + THR - 1) / THR;
+    const int64_t nblk = RANK_SPLIT * ((a.M + THR - 1) / THR);
     const int64_t slices = nblk / E > 0 ? nblk / E : 1;
     if (bid >= E * slices) return;
     const int64_t p = (bid % E) * THR + threadIdx.x, slice = bid / E;
@@ -216,6 +217,7 @@ SelArgs ubqp_sel_args(int32_t n, int64_t M, int64_t S, uint64_t run_seed, const 
 
 int64_t ubqp_seed_blocks(const SelArgs &a) { return (a.S * a.W + THR - 1) / THR; }
 int64_t ubqp_cand_blocks(const SelArgs &a) { return (a.M + THR - 1) / THR; }
+int64_t ubqp_rank_blocks(const SelArgs &a) { return RANK_SPLIT * ((a.M + THR - 1) / THR); }
 
 hipError_t ubqp_launch_seed_init(hipStream_t st, const SelArgs &a)
 {
@@ -238,10 +240,11 @@ hipError_t ubqp_launch_dump_batch(hipStream_t st, const SelArgs *args, const int
 }
 
 hipError_t ubqp_launch_select_batch(hipStream_t st, const SelArgs *args, const int64_t *cand_prefix,
-                                    int64_t cand_blocks, const int64_t *seed_prefix, int64_t seed_blocks, int count)
+                                    int64_t cand_blocks, const int64_t *rank_prefix, int64_t rank_blocks,
+                                    const int64_t *seed_prefix, int64_t seed_blocks, int count)
 {
     hipLaunchKernelGGL(incumbent_b, dim3(count), dim3(THR), 0, st, args, count);
-    hipLaunchKernelGGL(rank_b, dim3((unsigned)cand_blocks), dim3(THR), 0, st, args, cand_prefix, count);
+    hipLaunchKernelGGL(rank_b, dim3((unsigned)rank_blocks), dim3(THR), 0, st, args, rank_prefix, count);
     hipLaunchKernelGGL(place_b, dim3((unsigned)cand_blocks), dim3(THR), 0, st, args, cand_prefix, count);
     hipLaunchKernelGGL(seed_fill_b, dim3((unsigned)seed_blocks), dim3(THR), 0, st, args, seed_prefix, count);
     hipLaunchKernelGGL(advance_b, dim3((count + 63) / 64), dim3(64), 0, st, args, count);

@@ -328,6 +328,7 @@ SelArgs ubqp_sel_args(int32_t n, int64_t M, int64_t S, uint64_t run_seed, const 
                       uint64_t *seeds, int64_t *stats, const uint64_t *deriv_x, int64_t *f_dump);
 int64_t ubqp_seed_blocks(const SelArgs &a);
 int64_t ubqp_cand_blocks(const SelArgs &a);
+int64_t ubqp_rank_blocks(const SelArgs &a);
 hipError_t ubqp_launch_seed_init(hipStream_t st, const SelArgs &a);
 hipError_t ubqp_launch_seed_init_batch(hipStream_t st, const SelArgs *args, const int64_t *seed_prefix, int count,
                                        int64_t seed_blocks);
@@ -336,4 +337,5 @@ hipError_t ubqp_launch_dump_batch(hipStream_t st, const SelArgs *args, const int
 // incumbent update + statistics, ranking and placement into seeds 1.., seed 0 and random fill,
 // generation counter
 hipError_t ubqp_launch_select_batch(hipStream_t st, const SelArgs *args, const int64_t *cand_prefix,
-                                    int64_t cand_blocks, const int64_t *seed_prefix, int64_t seed_blocks, int count);
+                                    int64_t cand_blocks, const int64_t *rank_prefix, int64_t rank_blocks,
+                                    const int64_t *seed_prefix, int64_t seed_blocks, int count);
