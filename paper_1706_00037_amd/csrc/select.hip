@@ -135,13 +135,14 @@ __device__ void rank_body(const SelArgs &a, int64_t bid)
 // (passer, word) pairs, so consecutive threads copy consecutive words of a row.
 __device__ void place_body(const SelArgs &a, int64_t bid)
 {
-    const int64_t P = a.scal->npass;
-    const int64_t nblk = (a.M + THR - 1) / THR;
-    const int64_t total = P * a.W;
-    for (int64_t k = bid * THR + threadIdx.x; k < total; k += nblk * THR) {
-        const int64_t p = k / a.W, w = k - p * a.W;
+    // indices fit 32 bits (P W <= M W <= 2^29): 32-bit division
+    const uint32_t P = (uint32_t)a.scal->npass, W = (uint32_t)a.W;
+    const uint32_t nblk = (uint32_t)((a.M + THR - 1) / THR);
+    const uint32_t total = P * W;
+    for (uint32_t k = (uint32_t)bid * THR + threadIdx.x; k < total; k += nblk * THR) {
+        const uint32_t p = k / W, w = k - p * W;
         const int64_t r = a.rank[p];
-        if (r < a.S - 1) a.seeds[(1 + r) * a.W + w] = a.X[(int64_t)a.idx[p] * a.W + w];
+        if (r < a.S - 1) a.seeds[(1 + r) * W + w] = a.X[(int64_t)a.idx[p] * W + w];
     }
 }
 
