@@ -83,15 +83,17 @@ __device__ inline int32_t max16(const v16i &v)
     return max(ab, de);
 }
 
-// Largest value over the wave (DPP within rows of 16, then the four row leaders).
+// Largest value over the wave (DPP within rows of 16, then across rows by row broadcasts).
 __device__ inline int32_t wave_max_i32(int32_t v)
 {
     v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
     v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
     v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
     v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
-    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+    // every lane holds its row's maximum; fold the rows into the last one
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15 into rows 1, 3
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31 into rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Column ownership of the int8 ascent: lane l owns [l PL, (l+1) PL), PL = 16 NB.
