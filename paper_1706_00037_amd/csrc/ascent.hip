@@ -83,6 +83,40 @@ __device__ inline int32_t max16(const v16i &v)
     return max(ab, de);
 }
 
+// Largest of the lane's 16 NB keys: chains of three-input maxima over groups of
+// 15 keys (each maximum takes two new keys) and a group of the rest, then a tree
+// over the groups' results -- ceil((16 NB - 1) / 2) instructions in all.
+template <int NB> __device__ inline int32_t lane_max(const v16i (&kk)[NB])
+{
+    constexpr int N = 16 * NB, G = N / 15, R = N - 15 * G;
+    int32_t acc[G + 1];
+#pragma unroll
+    for (int g = 0; g <= G; g++) {
+        const int lo = 15 * g, cnt = g < G ? 15 : R;
+        if (cnt == 0) continue;
+        int32_t m = kk[lo / 16][lo % 16];
+        int k = 1;
+        if (cnt % 2 == 0) {
+            m = max(m, kk[(lo + 1) / 16][(lo + 1) % 16]);
+            k = 2;
+        }
+#pragma unroll
+        for (; k + 1 < cnt + 1; k += 2)
+            m = max(max(m, kk[(lo + k) / 16][(lo + k) % 16]), kk[(lo + k + 1) / 16][(lo + k + 1) % 16]);
+        acc[g] = m;
+    }
+    constexpr int A = R > 0 ? G + 1 : G;
+    int32_t best = acc[0];
+    int a = 1;
+    if (A % 2 == 0) {
+        best = max(best, acc[1]);
+        a = 2;
+    }
+#pragma unroll
+    for (; a + 1 < A + 1; a += 2) best = max(max(best, acc[a]), acc[a + 1]);
+    return best;
+}
+
 // Largest value over the wave (DPP within rows of 16, then across rows by row broadcasts).
 __device__ inline int32_t wave_max_i32(int32_t v)
 {
@@ -151,13 +185,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
     int32_t V;
     __builtin_amdgcn_s_waitcnt(WAIT_VM_LGKM_0);
     for (;;) {
-        int32_t bmax[NB];
-#pragma unroll
-        for (int b = 0; b < NB; b++) bmax[b] = max16(kk[b]);
-        int32_t best = bmax[0];
-#pragma unroll
-        for (int b = 1; b + 1 < NB; b += 2) best = max(max(best, bmax[b]), bmax[b + 1]);
-        if ((NB & 1) == 0) best = max(best, bmax[NB - 1]);
+        const int32_t best = lane_max<NB>(kk);
         const int32_t ld = best >> 8;
         V = wave_max_i32(ld);
         if (V <= 0 || flips >= cap) break;
