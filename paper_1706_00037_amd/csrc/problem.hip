@@ -192,7 +192,7 @@ hipError_t ubqp_queue_zero(hipStream_t st, void *p, int64_t words)
     return hipGetLastError();
 }
 
-int ubqp_check_verdict(ubqp_ctx *ctx, const ubqp_check_flags &fl, int32_t n)
+int ubqp_check_outcome(ubqp_ctx *ctx, const ubqp_check_flags &fl, int32_t n)
 {
     if (fl.bits & UBQP_CHECK_RANGE) {
         const long long k = (long long)fl.first[1];
@@ -227,7 +227,7 @@ int ubqp_problem_create_typed(ubqp_ctx *ctx, int32_t n, const void *q, int32_t e
     UBQP_HIP_TRY(ctx, ubqp_queue_problem_check(st, stage, elem_bytes, n, fl));
     UBQP_HIP_TRY(ctx, hipMemcpyAsync(&hf, fl, sizeof hf, hipMemcpyDeviceToHost, st));
     UBQP_HIP_TRY(ctx, hipStreamSynchronize(st));
-    UBQP_TRY(ubqp_check_verdict(ctx, hf, n));
+    UBQP_TRY(ubqp_check_outcome(ctx, hf, n));
     ubqp_problem *p = new (std::nothrow) ubqp_problem();
     if (!p) return ubqp_fail(ctx, UBQP_ENOMEM, "host allocation");
     p->ctx = ctx;

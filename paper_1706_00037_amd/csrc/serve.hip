@@ -305,7 +305,7 @@ hipError_t poll_uploads(ubqp_server *s)
         if (q != hipSuccess) return q;
         s->uploading.erase(s->uploading.begin() + (ptrdiff_t)i);
         const ubqp_check_flags fl = *(const ubqp_check_flags *)(s->slots[(size_t)r->slot].pin + PIN_FLAGS);
-        const int v = ubqp_check_verdict(nullptr, fl, r->n);
+        const int v = ubqp_check_outcome(nullptr, fl, r->n);
         if (v != UBQP_OK) {
             {
                 std::lock_guard<std::mutex> lk(s->m);

@@ -142,7 +142,7 @@ hipError_t ubqp_queue_problem_build(hipStream_t st, const void *stage, int elem,
 // Queue a fill of `words` 32-bit zeros.
 hipError_t ubqp_queue_zero(hipStream_t st, void *p, int64_t words);
 // UBQP_OK, or the error (with message) that the check flags report.
-int ubqp_check_verdict(ubqp_ctx *ctx, const ubqp_check_flags &fl, int32_t n);
+int ubqp_check_outcome(ubqp_ctx *ctx, const ubqp_check_flags &fl, int32_t n);
 
 // ---- per-instance kernel arguments --------------------------------------------
 // Every kernel body takes one of these for its instance; single-instance
