@@ -214,6 +214,9 @@ ASCENT_CASES = [
     (6000, 8, 2, 0.3, -100, 100, 0),      # one plane, six blocks: two waves per candidate
     (4500, 12, 3, 0.6, -4, 4, 0),         # two waves per candidate, many ties across the waves
     (7000, 6, 2, 0.5, -100, 100, 9),      # two waves per candidate, capped
+    (3500, 12, 2, 0.4, -100, 100, 0),     # one plane, four blocks of 16 columns per lane
+    (4000, 10, 2, 0.3, -32768, 32767, 0),  # two planes, four blocks
+    (3100, 10, 3, 0.5, -100, 100, 5),     # one plane, four blocks, capped
 ]
 
 
