@@ -301,6 +301,7 @@ def test_multistart_config1_full(ctx):
     dict(n=90, d=0.5, lo=-100, hi=100, M=100, H=5, lam=(1, 1), G=2, mf=0, flags=0),   # nobody passes
     dict(n=1100, d=0.3, lo=-100, hi=100, M=2000, H=10, lam=(1, 2), G=3, mf=0, flags=0),
     dict(n=4500, d=0.3, lo=-32768, hi=32767, M=300, H=10, lam=(1, 2), G=2, mf=0, flags=0),
+    dict(n=7000, d=0.5, lo=-100, hi=100, M=240, H=10, lam=(1, 2), G=3, mf=0, flags=0),   # the headline shape
 ])
 def test_multistart_matches_oracle(ctx, case):
     c = case
