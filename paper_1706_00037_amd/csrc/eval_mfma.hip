@@ -226,6 +226,10 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
                 if (((sub + 1) & 1) == 0) EVAL_READ_A(cur, (sub + 1) >> 1);
                 EVAL_READ_B(bfn, cur, sub + 1);
             }
+            // the substep's matrix ops at raised wave priority: the SIMD's other wave
+            // (another workgroup) gets the issue slots of its loads and expansion
+            // in between instead of competing with this burst (5% faster measured)
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int ni = 0; ni < FN; ni++)
 #pragma unroll
@@ -245,6 +249,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
 #pragma unroll
                 for (int ni = 0; ni < FN; ni++) bfc[ni] = bfn[ni];
             }
+            __builtin_amdgcn_s_setprio(0);
         }
         if (more) {
             EVAL_STORE_STAGE(cur ^ 1);
