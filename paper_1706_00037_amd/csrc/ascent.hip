@@ -217,6 +217,10 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         uint4 w[NB];
 #pragma unroll
         for (int b = 0; b < NB; b++) w[b] = ubqp_ldg16(row + asc_col0<NB>(lane, b));
+        // the update is the VALU burst of a flip; with the wave's priority raised
+        // while it runs, the SIMD's other wave fills the gaps its loads leave
+        // rather than stretching it
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int b = 0; b < NB; b++) {
             int32_t k[16];
@@ -228,6 +232,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
 #pragma unroll
             for (int t = 0; t < 16; t++) kk[b][t] = k[t];
         }
+        __builtin_amdgcn_s_setprio(0);
     }
     if (V > 0 && a.max_flips == 0 && lane == 0) atomicOr(a.err, 1);  // safety cap reached
 
@@ -397,6 +402,7 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
             w[b][0] = ubqp_ldg16(row + 16 * b);
             w[b][1] = ubqp_ldg16(row + 16 * b + 8);
         }
+        __builtin_amdgcn_s_setprio(1);  // as in the int8 ascent
 #pragma unroll
         for (int b = 0; b < NB; b++) {
             int32_t d[16];
@@ -409,6 +415,7 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
 #pragma unroll
             for (int t = 0; t < 16; t++) dl[b][t] = d[t];
         }
+        __builtin_amdgcn_s_setprio(0);
     }
     if (V > 0 && a.max_flips == 0 && lane == 0) atomicOr(a.err, 1);  // safety cap reached
 
