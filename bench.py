@@ -43,7 +43,7 @@ PAPER_TABLE1_S = {2500: 0.7, 5000: 2.0, 6000: 3.0, 7000: 3.5}   # GPU seconds pe
 # counter passes summarised in profiles/counters_n7000_M16384.md (FETCH_SIZE and
 # WRITE_SIZE, calibrated against a 1 GiB device copy).  Valid for the kernels as
 # they were when the counters were taken; set to None when a kernel changes.
-TRAFFIC_GB = {"ascent": None, "eval": 0.576}
+TRAFFIC_GB = {"ascent": 4.129, "eval": 0.575}
 
 
 def log(msg):
