@@ -479,7 +479,7 @@ def main():
     # ---- the small and the timing-table configurations end to end ------------------------
     # n=500 (M=1000) and n=2500 (M=65536), 20 generations each from generation 0, with
     # the mean phase times of the generations after the first
-    configs = {}
+    small_runs = {}
     if not args.no_configs:
         for name in ("n500_d0.10_M1000", "n2500_d0.10_M65536"):
             cc = WORKLOADS[name]
@@ -494,7 +494,7 @@ def main():
             torch.cuda.synchronize()
             tc = (time.perf_counter() - tc0) * 1e3
             stc = rc["stats"]
-            configs[name] = dict(n=cc["n"], M=cc["M"], G=cc["G"], ms_total_call=tc,
+            small_runs[name] = dict(n=cc["n"], M=cc["M"], G=cc["G"], ms_total_call=tc,
                                  ms_total_events=float(rc["gen_ms"][-1]),
                                  ms_per_generation=float(rc["gen_ms"][-1]) / cc["G"],
                                  evals_per_s=cc["M"] * cc["G"] / (tc * 1e-3), best_f=rc["best_f"],
@@ -502,9 +502,9 @@ def main():
                                  phases_ms_after_gen0={ph: float(rc["phase_ms"][1:, i].mean())
                                                        for i, ph in enumerate(ubqp.PHASES)})
             del pc
-            log(f"[bench] {name}: {cc['G']} generations in {tc:.2f} ms ({configs[name]['evals_per_s']:.3g} evals/s), "
+            log(f"[bench] {name}: {cc['G']} generations in {tc:.2f} ms ({small_runs[name]['evals_per_s']:.3g} evals/s), "
                 f"best f {rc['best_f']}, phases after generation 0 "
-                f"{ {k: round(v, 4) for k, v in configs[name]['phases_ms_after_gen0'].items()} }")
+                f"{ {k: round(v, 4) for k, v in small_runs[name]['phases_ms_after_gen0'].items()} }")
 
     # ---- the headline workload with blending diversification -------------------------
     blend = None
@@ -667,7 +667,7 @@ def main():
                       "traffic_gb_per_launch": TRAFFIC_GB["eval"]},
         "e1_replica": e1_rep,
         "lambda_sweep": lam_sweep,
-        "configs": configs,
+        "configs": small_runs,
         "blend": blend,
         "sequential": seq,
         "relink": relink,
