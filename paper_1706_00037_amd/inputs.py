@@ -77,3 +77,29 @@ WORKLOADS = {
     "n7000_d0.50_M16384": dict(n=7000, density=0.50, lo=-100, hi=100, inst_seed=3001, run_seed=3,
                                M=16384, H=10, lam=(1, 2), G=20),
 }
+
+
+# Request stream of the serving workload: request r has n ~ U{500..7000}, density
+# ~ U[0.05, 1] (both from one PCG64 stream, seed 5), coefficients uniform in
+# [-100, 100] \ {0}, instance seed 5000 + r, run seed 5000 + r, M = 4096, H = 10,
+# lambda = 1/2, G = 10.
+SERVE_PARAMS = dict(M=4096, H=10, lam_num=1, lam_den=2, G=10)
+
+
+def serving_requests(count: int, seed: int = 5):
+    """The first `count` requests of the serving workload: list of dicts with n,
+    density, inst_seed and run_seed (the instance itself is make_instance(n,
+    density, -100, 100, inst_seed))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.integers(500, 7001, size=count)
+    ds = rng.uniform(0.05, 1.0, size=count)
+    return [dict(n=int(ns[r]), density=float(ds[r]), inst_seed=5000 + r, run_seed=5000 + r) for r in range(count)]
+
+
+# A subset of the batched workload's shape drawn host-side: int16 coefficients
+# over the whole range (two int8 planes), n spread over [1000, 7000], the three
+# densities, M = 4096, H = 10, lambda = 1/2, G = 10, instance seed 4001 + k, run
+# seed 4000 + k.
+BATCH_SUBSET = [dict(n=1000, density=0.1), dict(n=2900, density=1.0), dict(n=4800, density=0.5),
+                dict(n=7000, density=0.1)]
+BATCH_PARAMS = dict(M=4096, H=10, lam_num=1, lam_den=2, G=10)
