@@ -36,14 +36,35 @@ sys.path.insert(0, ROOT)
 METRIC = "exact xQx evals/s at n=7000 (vs plain); served solves/s + p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0      # dense int8 matrix-core peak, TOP/s
-VALU_INT32_TOPS = 39.3       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, int32 ops/s / 1e12
-L2_PEAK_GBS = 39322.0        # 8 XCD x 16 L2 channels x 128 B/clock x 2.4 GHz (derived, read side)
+VALU_INT32_TOPS = 39.3       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz: int32 lane-operations/s / 1e12
 PAPER_TABLE1_S = {2500: 0.7, 5000: 2.0, 6000: 3.0, 7000: 3.5}   # GPU seconds per 1000 evals
-# Memory traffic per launch of the two main kernels at this workload, from the two
-# counter passes summarised in profiles/counters_n7000_M16384.md (FETCH_SIZE and
-# WRITE_SIZE, calibrated against a 1 GiB device copy).  Valid for the kernels as
-# they were when the counters were taken; set to None when a kernel changes.
-TRAFFIC_GB = {"ascent": 4.129, "eval": 0.575}
+# Per-launch memory traffic of the main kernels at the headline workload comes from
+# the two counter passes (FETCH_SIZE, WRITE_SIZE; calibrated against a 1 GiB device
+# copy) summarised in this file, together with the SHA-256 of each kernel's source
+# at the time; a kernel whose source has changed since gets traffic null.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "counters_n7000_M16384.md")
+CSRC = os.path.join(ROOT, "paper_1706_00037_amd", "csrc")
+
+
+def load_traffic():
+    """{kernel: {"gb": fetched + written GB per launch, ...}} for the kernels whose
+    source is unchanged since the counters were taken; others map to None."""
+    import hashlib
+    import re
+    out = {}
+    try:
+        text = open(TRAFFIC_FILE).read()
+        block = re.search(r"```json\n(.*?)\n```", text, flags=re.S).group(1)
+        table = json.loads(block)
+    except (OSError, AttributeError, ValueError):
+        return out
+    for name, rec in table.items():
+        try:
+            sha = hashlib.sha256(open(os.path.join(CSRC, rec["source"]), "rb").read()).hexdigest()
+        except OSError:
+            sha = None
+        out[name] = rec if sha == rec.get("source_sha256") else None
+    return out
 
 
 def log(msg):
@@ -65,6 +86,8 @@ def parse():
     ap.add_argument("--no-blend", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--no-relink", action="store_true")
+    ap.add_argument("--no-gen0", action="store_true", help="skip the generation-0 leg and the population summary")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the MFMA and read-bandwidth measurements")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -144,11 +167,66 @@ def cpu_baseline(Q, n, M, P_per_gen, flips_per_gen, threads):
                 host_logical_cpus=os.cpu_count())
 
 
-def make_request_instance(torch, n, density, seed):
-    """Symmetric int8 instance for the serving trace, drawn on the device with
-    torch's seeded Philox generator and copied to page-locked host memory:
-    upper-triangle mask Bernoulli(density) (diagonal included), values uniform in
-    [-100, 100] \\ {0}, mirrored."""
+def passers_of(f, lam_num, lam_den):
+    """Boolean mask of the candidates whose objective clears T(lambda) over the
+    population f (exact integers; used only to describe the timed populations)."""
+    M = len(f)
+    s, mx = int(sum(int(v) for v in f)), int(max(f))
+    rhs = (lam_den - lam_num) * s + lam_num * M * mx
+    return np.array([lam_den * M * int(v) > rhs for v in f])
+
+
+def population_summary(ctx, prob, kw, gens):
+    """Distinct objective values among all candidates and among the passers of each
+    of the generations `gens` of the run kw (a second, identical run with an
+    objective dump; distinct values bound the distinct solutions from below)."""
+    import torch
+    G, M = kw["G"], kw["M"]
+    dump = torch.zeros(G * M, dtype=torch.int64, device="cuda")
+    ctx.multistart(prob, f_dump=dump, **kw)
+    fd = dump.cpu().numpy().reshape(G, M)
+    out = []
+    for g in gens:
+        mask = passers_of(fd[g], kw["lam_num"], kw["lam_den"])
+        out.append(dict(generation=int(g), distinct_objectives=int(len(np.unique(fd[g]))),
+                        passers=int(mask.sum()), distinct_passer_objectives=int(len(np.unique(fd[g][mask])))))
+    return out
+
+
+def gen0_leg(ctx, ubqp, prob, c, lam_num, lam_den, K):
+    """Generation 0 from random seeds, K times with distinct run seeds (1000 + k):
+    the population is 820 random seeds x 20 Glover candidates, all distinct, and
+    the passers are distinct solutions far from local optima.  Per-phase times from
+    stream events, as for the headline."""
+    n, M, H = c["n"], c["M"], c["H"]
+    gen_ms, phases, st = [], [], []
+    for k in range(K):
+        r = ctx.run(prob, M=M, H=H, lam_num=lam_num, lam_den=lam_den, G=1, run_seed=1000 + k,
+                    flags=ubqp.UBQP_TIMING)
+        r.step(1)
+        rr = r.result()
+        r.close()
+        gen_ms.append(float(rr["gen_ms"][0]))
+        phases.append(rr["phase_ms"][0])
+        st.append(rr["stats"][0])
+    ph = np.array(phases)
+    st = np.array(st)
+    pop = population_summary(ctx, prob, dict(M=M, H=H, lam_num=lam_num, lam_den=lam_den, G=1, run_seed=1000), [0])
+    ms = float(np.mean(gen_ms))
+    return dict(runs=K, ms_per_generation=ms, evals_per_s=M / (ms * 1e-3),
+                phases_ms={name: float(ph[:, i].mean()) for i, name in enumerate(ubqp.PHASES)},
+                passers_per_gen=float(st[:, 2].mean()), flips_per_gen=float(st[:, 3].mean()),
+                population=pop[0],
+                note="generation 0 of K runs with distinct run seeds: random seeds, every candidate and "
+                     "passer a distinct solution (stream-event time from the seeds to the end of the "
+                     "generation)")
+
+
+def make_request_instance(torch, n, density, seed, out):
+    """Symmetric int8 instance of the serving workload, drawn on the device with
+    torch's seeded Philox generator (upper-triangle mask Bernoulli(density),
+    diagonal included, values uniform in [-100, 100] \\ {0}, mirrored) and copied
+    into the host array `out` (int8 [n, n], page-locked)."""
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
     u = torch.randint(0, 200, (n, n), generator=g, device="cuda", dtype=torch.int16)
@@ -156,35 +234,71 @@ def make_request_instance(torch, n, density, seed):
     keep = torch.rand((n, n), generator=g, device="cuda") < density
     U = torch.triu(torch.where(keep, v, torch.zeros_like(v)))
     Q = (U + torch.tril(U.t(), -1)).to(torch.int8)
-    host = torch.empty((n, n), dtype=torch.int8, pin_memory=True)
-    host.copy_(Q)
-    return host
+    torch.from_numpy(out).copy_(Q)
 
 
-def serving_bench(ctx, ubqp, torch, R=300, warm=20, rate=200.0, distinct=32, max_active=32,
-                  pool_gib=48, seed=5):
-    """Poisson arrivals of multi-start solve requests (n ~ U{500..7000}, density ~
-    U[0.05, 1], [-100, 100], M=4096, H=10, lambda=1/2, G=10) against the request
-    server, then against the same server admitting one request at a time (the
-    plain one-at-a-time GPU loop).  Latency = result on the host - scheduled
-    arrival (upload included)."""
+class PinnedArena:
+    """One page-locked host block (hipHostMalloc of the HIP runtime torch loaded)
+    handed out as int8 [n, n] arrays; freed by close()."""
+
+    def __init__(self, nbytes):
+        import ctypes
+        self.ct = ctypes
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipHostMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_uint]
+        self.hip.hipHostFree.argtypes = [ctypes.c_void_p]
+        self.ptr = ctypes.c_void_p()
+        rc = self.hip.hipHostMalloc(ctypes.byref(self.ptr), ctypes.c_size_t(nbytes), 0)
+        if rc != 0 or not self.ptr.value:
+            raise RuntimeError(f"hipHostMalloc of {nbytes} bytes failed ({rc})")
+        self.nbytes, self.off = nbytes, 0
+
+    def take(self, n):
+        size = n * n
+        assert self.off + size <= self.nbytes
+        buf = (self.ct.c_int8 * size).from_address(self.ptr.value + self.off)
+        self.off += (size + 255) // 256 * 256
+        return np.ctypeslib.as_array(buf).reshape(n, n)
+
+    def close(self):
+        if self.ptr.value:
+            self.hip.hipHostFree(self.ptr)
+            self.ptr = self.ct.c_void_p()
+
+
+def serving_bench(ctx, ubqp, torch, R=300, warm=20, rate=200.0, max_active=32, pool_gib=48, seed=5):
+    """Poisson arrivals of multi-start solve requests (the serving request stream:
+    request r has n ~ U{500..7000}, density ~ U[0.05, 1], coefficients in
+    [-100, 100], M=4096, H=10, lambda=1/2, G=10, a fresh instance drawn with seed
+    5000 + r and run seed 5000 + r) against the request server, then against the
+    same server admitting one request at a time (the plain one-at-a-time GPU loop),
+    on the same trace.  Every instance is drawn before the clock starts into
+    page-locked host memory (a request's coefficients are in host memory when it
+    arrives); latency = result on the host - scheduled arrival, upload included."""
     import threading
+    from paper_1706_00037_amd.inputs import SERVE_PARAMS, serving_requests
 
-    rng = np.random.Generator(np.random.PCG64(seed))
-    ns = rng.integers(500, 7001, size=distinct)
-    ds = rng.uniform(0.05, 1.0, size=distinct)
-    log(f"[serve] generating {distinct} distinct instances into page-locked memory")
+    reqs = serving_requests(warm + R, seed=seed)
+    total = sum((q["n"] * q["n"] + 255) // 256 * 256 for q in reqs)
+    log(f"[serve] drawing {warm + R} fresh instances ({total / 2**30:.1f} GiB) into page-locked memory")
+    t0 = time.perf_counter()
+    arena = PinnedArena(total)
     inst = []
-    for k in range(distinct):
-        inst.append(make_request_instance(torch, int(ns[k]), float(ds[k]), 5000 + k))
+    for q in reqs:
+        a = arena.take(q["n"])
+        make_request_instance(torch, q["n"], q["density"], q["inst_seed"], a)
+        inst.append(a)
+    torch.cuda.synchronize()
+    log(f"[serve] instances ready in {time.perf_counter() - t0:.1f} s")
+    rng = np.random.Generator(np.random.PCG64(seed))
     gaps = rng.exponential(1.0 / rate, size=R)
     offs = np.cumsum(gaps) - gaps[0]
-    pr = lambda r: dict(M=4096, H=10, lam_num=1, lam_den=2, G=10, run_seed=5000 + r)
+    pr = lambda r: dict(SERVE_PARAMS, run_seed=reqs[r]["run_seed"])
 
     def run_trace(active):
         srv = ctx.server(pool_bytes=pool_gib << 30, max_active=active)
         try:
-            ids = [srv.submit(inst[r % distinct], **pr(10**6 + r)) for r in range(warm)]
+            ids = [srv.submit(inst[r], **pr(r)) for r in range(warm)]
             got = 0
             while got < len(ids):
                 got += len(srv.wait(timeout_s=5.0))
@@ -199,14 +313,14 @@ def serving_bench(ctx, ubqp, torch, R=300, warm=20, rate=200.0, distinct=32, max
             th.start()
             t0 = time.monotonic_ns() + 20_000_000
             sched = {}
-            for r in range(R):
-                at = t0 + int(offs[r] * 1e9)
+            for k in range(R):
+                at = t0 + int(offs[k] * 1e9)
                 while True:
                     dt = at - time.monotonic_ns()
                     if dt <= 0:
                         break
                     time.sleep(min(dt, 2_000_000) / 1e9)
-                i = srv.submit(inst[r % distinct], **pr(r))
+                i = srv.submit(inst[warm + k], **pr(warm + k))
                 sched[i] = at
             th.join(timeout=600)
             stop.set()
@@ -224,11 +338,11 @@ def serving_bench(ctx, ubqp, torch, R=300, warm=20, rate=200.0, distinct=32, max
                     pool_high_gib=st["pool_high"] / 2**30, max_active=active)
 
     def run_burst(active, count=120):
-        """Capacity: `count` requests submitted at once; solves/s over the drain."""
+        """Capacity: `count` requests (the first timed ones) submitted at once; solves/s over the drain."""
         srv = ctx.server(pool_bytes=pool_gib << 30, max_active=active)
         try:
             t0 = time.monotonic_ns()
-            ids = [srv.submit(inst[r % distinct], **pr(2 * 10**6 + r)) for r in range(count)]
+            ids = [srv.submit(inst[warm + r], **pr(warm + r)) for r in range(count)]
             done = {}
             while len(done) < count:
                 for x in srv.wait(timeout_s=5.0):
@@ -238,21 +352,25 @@ def serving_bench(ctx, ubqp, torch, R=300, warm=20, rate=200.0, distinct=32, max
         end = max(x["t_done_ns"] for x in done.values())
         return count / ((end - t0) / 1e9)
 
-    log(f"[serve] trace: {R} requests at {rate}/s, continuous batching (max_active={max_active})")
-    batched = run_trace(max_active)
-    log(f"[serve] batched: {batched}")
-    log("[serve] same trace, one request at a time")
-    plain = run_trace(1)
-    log(f"[serve] one at a time: {plain}")
-    cap_b, cap_p = run_burst(max_active), run_burst(1)
+    try:
+        log(f"[serve] trace: {R} requests at {rate}/s, continuous batching (max_active={max_active})")
+        batched = run_trace(max_active)
+        log(f"[serve] batched: {batched}")
+        log("[serve] same trace, one request at a time")
+        plain = run_trace(1)
+        log(f"[serve] one at a time: {plain}")
+        cap_b, cap_p = run_burst(max_active), run_burst(1)
+    finally:
+        arena.close()
     log(f"[serve] capacity (120 requests at once): {cap_b:.1f} solves/s batched, {cap_p:.1f} one at a time")
     batched["capacity_solves_per_s"] = cap_b
     plain["capacity_solves_per_s"] = cap_p
+    ns = np.array([q["n"] for q in reqs[warm:]])
     return dict(batched=batched, one_at_a_time=plain, requests=R, warmup_requests=warm, rate_per_s=rate,
-                distinct_instances=distinct,
-                workload=f"Poisson {rate:.0f} req/s; n ~ U{{500..7000}}, density ~ U[0.05,1], [-100,100], "
-                         f"M=4096, H=10, lambda=1/2, G=10; {distinct} distinct seeded instances cycled, "
-                         f"a fresh run seed and a fresh upload per request")
+                distinct_instances=warm + R, mean_n=float(ns.mean()),
+                workload=f"Poisson {rate:.0f} req/s; request r: n ~ U{{500..7000}}, density ~ U[0.05,1], "
+                         f"[-100,100], M=4096, H=10, lambda=1/2, G=10, a fresh instance (seed 5000+r) and "
+                         f"run seed per request, uploaded by the server from page-locked host memory")
 
 
 def make_wide_instance(torch, n, density, seed):
@@ -304,6 +422,16 @@ def batched_bench(ctx, ubqp, torch, count=64, G=6, warm=2, seed=4):
     row_bytes = float(sum(r["stats"][warm:, 3].sum() * 2 * int(ns[k]) for k, r in enumerate(res))) / (G - warm)
     log(f"[batch] batched: {t_batch * 1e3:.2f} ms per generation of all {count} instances, "
         f"{flips:.0f} flips per generation")
+    # the same batch with stream events around every phase (direct launches): the
+    # ascent kernels' share of a generation and their row rate
+    bt = ctx.batch(probs, [dict(p, flags=p["flags"] | ubqp.UBQP_TIMING) for p in params])
+    bt.step(G)
+    rt = bt.result(0)
+    bt.close()
+    ph_t = rt["phase_ms"][warm:]
+    phases_b = {name: float(ph_t[:, i].mean()) for i, name in enumerate(ubqp.PHASES)}
+    t_asc = phases_b["ascent_kernel"] * 1e-3
+    log(f"[batch] phases with events (direct launches): {phases_b}")
     # the same generations, one instance after another
     t_seq = 0.0
     for k in range(count):
@@ -321,7 +449,13 @@ def batched_bench(ctx, ubqp, torch, count=64, G=6, warm=2, seed=4):
     t_seq /= (G - warm)
     log(f"[batch] one instance at a time: {t_seq * 1e3:.2f} ms per generation of all {count}")
     return dict(instances=count, ms_per_generation=t_batch * 1e3, evals_per_s=count * 4096 / t_batch,
-                flips_per_generation=flips, ascent_row_gbs_if_all_time=row_bytes / t_batch / 1e9,
+                flips_per_generation=flips, phases_ms_direct=phases_b,
+                ascent_roofline=dict(kernel="ascent_i16_batched (two int8 planes: int16 rows)", bound="hbm",
+                                     algorithmic_gb=row_bytes / 1e9, avg_ms=t_asc * 1e3,
+                                     achieved=row_bytes / t_asc / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                                     frac=row_bytes / t_asc / 1e9 / HBM_PEAK_GBS,
+                                     note="2 n bytes of the int16 ascent matrix per flip; the 64 matrices "
+                                          "(about 2.2 GB) exceed the Infinity Cache, so rows stream from HBM"),
                 dense_tops=ops / t_batch / 1e12, sequential_ms_per_generation=t_seq * 1e3,
                 speedup_vs_sequential=t_seq / t_batch, timed_generations=G - warm,
                 eval_variants=chosen, tuning_s=t_tune,
@@ -453,6 +587,16 @@ def main():
     phase_mean = {name: float(ph[:, i].mean()) for i, name in enumerate(ubqp.PHASES)}
     P_mean, flips_mean = float(st[:, 2].mean()), float(st[:, 3].mean())
     log(f"[bench] {wall_ms:.3f} ms/generation; phases {phase_mean}; P={P_mean:.0f} flips={flips_mean:.0f}")
+    pop_timed, gen0 = None, None
+    if not args.no_gen0:
+        kw_head = dict(M=M, H=H, lam_num=lam_num, lam_den=lam_den, G=G, run_seed=c["run_seed"])
+        pop_timed = population_summary(ctx, prob, kw_head, range(Wm, G))
+        log(f"[bench] timed populations: {pop_timed[0]} (first timed generation)")
+        # ---- generation 0 from random seeds: distinct candidates and passers ---------
+        gen0 = gen0_leg(ctx, ubqp, prob, c, lam_num, lam_den, max(3, min(K, 10)))
+        log(f"[bench] generation 0 from random seeds: {gen0['ms_per_generation']:.3f} ms "
+            f"({gen0['evals_per_s']:.3g} evals/s), phases {gen0['phases_ms']}, P={gen0['passers_per_gen']:.0f} "
+            f"flips={gen0['flips_per_gen']:.0f}")
 
     # ---- the other screening thresholds of the headline workload ----------------------
     lam_sweep = {}
@@ -552,43 +696,67 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     eval_ms = e0.elapsed_time(e1) / R
-    n_pad = prob.n_pad
-    useful_ops = 2.0 * M * n * n
-    exec_ops = 2.0 * M * n_pad * n_pad
-    log(f"[bench] eval alone {eval_ms:.3f} ms: {useful_ops / eval_ms / 1e9:.1f} TOP/s useful")
-    mfma_meas = ctx.mfma_peak()
-    log(f"[bench] int8 MFMA rate sustained on this device (registers only): {mfma_meas:.0f} TOP/s; the "
-        f"evaluation executes {useful_ops / 2 / eval_ms / 1e9 / mfma_meas:.3f} of it")
+    exec_ops, useful_ops = ctx.eval_ops(prob, M)      # executed by the kernel / the dense definition 2 n^2 M
+    log(f"[bench] eval alone {eval_ms:.3f} ms: {exec_ops / eval_ms / 1e9:.1f} TOP/s executed "
+        f"({exec_ops / eval_ms / 1e9 / INT8_PEAK_TOPS:.3f} of the int8 peak), "
+        f"{useful_ops / eval_ms / 1e9:.1f} TOP/s dense-equivalent")
+    mfma_meas, read_peaks = None, None
+    if not args.no_peaks:
+        mfma_meas = ctx.mfma_peak()
+        log(f"[bench] int8 MFMA rate sustained on this device (registers only): {mfma_meas:.0f} TOP/s; the "
+            f"evaluation executes {exec_ops / eval_ms / 1e9 / mfma_meas:.3f} of it")
+        # read bandwidth of the memory levels (streaming kernel): a buffer each XCD's
+        # L2 holds, one only the Infinity Cache holds, and HBM streaming
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        read_peaks = {"l2_2MiB": ctx.read_peak(2 << 20, 2 << 20, 4 << 20),
+                      "infinity_cache_128MiB": ctx.read_peak(128 << 20, 64 << 10, 1 << 20),
+                      "hbm_stream": ctx.read_peak(8 * cus * (2 << 20), 2 << 20, 2 << 20)}
+        log(f"[bench] measured read bandwidth (GB/s): {read_peaks}")
+    traffic = load_traffic()
 
     # ---- roofline of the dominant phase ------------------------------------------
     dom = max((k for k in phase_mean if k != "ascent_kernel"), key=phase_mean.get)
     if dom == "eval":
         t_ms = phase_mean["eval"]
-        ach = useful_ops / (t_ms * 1e-3) / 1e12
+        ach = exec_ops / (t_ms * 1e-3) / 1e12
+        tr = traffic.get("eval_batched<0,128>")
         roof = dict(kernel="eval_batched<0,128> (int8 MFMA, lower triangle, fused row dot)", bound="mfma",
                     achieved=ach, peak=INT8_PEAK_TOPS, unit="TFLOP/s", frac=ach / INT8_PEAK_TOPS,
-                    traffic=TRAFFIC_GB["eval"], traffic_unit="GB per launch (HBM/fabric, calibrated counters)",
-                    algorithmic="2 n^2 int8 ops per candidate x M candidates per launch",
+                    traffic=tr["gb"] if tr else None, traffic_unit="GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+                    algorithmic="int8 matrix-core ops the launch executes (lower triangle by column tiles)",
                     avg_launch_ms=t_ms)
     else:
-        # the ascent kernel alone (its launches in a generation, bracketed by stream
-        # events on the launch stream): every flip streams one row of the ascent
-        # matrix, n int8 entries, from the memory system; Delta stays in registers
+        # The ascent kernel alone (its launches in a generation, bracketed by stream
+        # events on the launch stream).  Per flip and variable the method does one
+        # update of Delta and one comparison of the argmax: 2 n int32 operations per
+        # flip, all on the vector ALUs (the row of Q it reads, n bytes, comes from L2
+        # or the Infinity Cache).  The bound is the vector-ALU issue rate.
         t_ms = phase_mean["ascent_kernel"]
-        byts = flips_mean * n
-        ach = byts / (t_ms * 1e-3) / 1e9
-        alu = flips_mean * n * 2.5 / (t_ms * 1e-3) / 1e12
+        ops = 2.0 * n * flips_mean
+        ach = ops / (t_ms * 1e-3) / 1e12
+        row_gb = flips_mean * n / 1e9
+        tr = traffic.get("ascent_i8_batched<7>")
+        mem = dict(algorithmic_row_gb=row_gb, row_gbs=row_gb / (t_ms * 1e-3),
+                   read_peak_gbs_measured=read_peaks)
+        if tr and read_peaks:
+            beyond = tr["fetch_gb"]
+            l2 = max(row_gb - beyond, 0.0)
+            t_lb = (l2 / read_peaks["l2_2MiB"] + beyond / read_peaks["infinity_cache_128MiB"]) * 1e3
+            mem.update(beyond_l2_gb=beyond, l2_served_gb=l2, lower_bound_ms=t_lb, frac=t_lb / t_ms,
+                       note="time the rows need at the measured L2 and Infinity Cache read rates, split as the "
+                            "counters split them, against the kernel's time")
         roof = dict(kernel="ascent_i8_batched<7> (steepest 1-flip ascent of every passer)",
-                    bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                    traffic=TRAFFIC_GB["ascent"], traffic_unit="GB per launch (HBM/fabric, calibrated counters)",
-                    algorithmic="n bytes of Q per flip x flips of the generation",
-                    algorithmic_gb_per_launch=byts / 1e9, avg_launch_ms=t_ms,
+                    bound="alu", achieved=ach, peak=VALU_INT32_TOPS, unit="TOP/s (int32 lane-operations)",
+                    frac=ach / VALU_INT32_TOPS, traffic=tr["gb"] if tr else None,
+                    traffic_unit="GB per launch beyond L2 (calibrated FETCH_SIZE + WRITE_SIZE)",
+                    algorithmic="2 n int32 operations per flip (Delta update and argmax comparison) x flips of "
+                                "the generation",
+                    algorithmic_tops_per_launch=ops / 1e12, avg_launch_ms=t_ms,
                     phase_ms_with_delta_init=phase_mean[dom], flips_per_s=flips_mean / (t_ms * 1e-3),
-                    valu_tops=alu, valu_frac=alu / VALU_INT32_TOPS,
-                    l2_peak_gbs_derived=L2_PEAK_GBS, frac_l2=ach / L2_PEAK_GBS,
-                    note="achieved counts every row a flip reads; L2 serves most of them (traffic beyond L2 "
-                         "is the counters' figure), so frac can exceed 1 against HBM; the per-wave flip chain "
-                         "(row read, then the column update) at two waves per SIMD is the limit")
+                    memory=mem,
+                    note="peak = 256 CU x 4 SIMD x 16 lanes x 2.4 GHz; the kernel issues about 2.5 vector "
+                         "instructions per variable and flip (multiply, multiply-add, half a three-input "
+                         "maximum) and each wave's flip chain waits on its row read in between")
 
     # ---- the paper's Table 1 replica: 1000 random solutions --------------------------
     e1_rep = {}
@@ -650,6 +818,10 @@ def main():
         "config": {"workload": f"n={n}, density {c['density']}, coefficients in [-100,100], M={M} candidates "
                                f"per generation (H={H}), lambda={lam_num}/{lam_den}, ascent to a local optimum; "
                                f"one step = one generation (diversify, eval, screen, ascent, select)",
+                   "population_note": "after the warm-up every seed is the incumbent (the next-seed rule's fixed "
+                                      "point), so a timed generation's candidates are the incumbent's 20 Glover "
+                                      "variants, each repeated; 'timed_population' gives the distinct objective "
+                                      "values, 'generation0' the rate from random seeds (all distinct)",
                    "n": n, "M": M, "H": H, "lambda": f"{lam_num}/{lam_den}", "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -658,13 +830,17 @@ def main():
         "passers_per_gen": P_mean,
         "flips_per_gen": flips_mean,
         "eval_only": {"ms": eval_ms, "evals_per_s": M / (eval_ms * 1e-3),
-                      "useful_tops": useful_ops / eval_ms / 1e9, "dense_padded_tops": exec_ops / eval_ms / 1e9,
-                      "frac_int8_peak": useful_ops / eval_ms / 1e9 / INT8_PEAK_TOPS,
-                      "executed_lower_triangle_tops": useful_ops / 2 / eval_ms / 1e9,
+                      "executed_ops": exec_ops, "executed_tops": exec_ops / eval_ms / 1e9,
+                      "frac_int8_peak": exec_ops / eval_ms / 1e9 / INT8_PEAK_TOPS,
+                      "dense_equivalent_ops": useful_ops, "dense_equivalent_tops": useful_ops / eval_ms / 1e9,
+                      "dense_equivalent_frac_int8_peak": useful_ops / eval_ms / 1e9 / INT8_PEAK_TOPS,
                       "mfma_peak_measured_tops": mfma_meas,
-                      "frac_measured_peak_useful": useful_ops / eval_ms / 1e9 / mfma_meas,
-                      "frac_measured_peak_executed": useful_ops / 2 / eval_ms / 1e9 / mfma_meas,
-                      "traffic_gb_per_launch": TRAFFIC_GB["eval"]},
+                      "frac_measured_peak_executed": exec_ops / eval_ms / 1e9 / mfma_meas if mfma_meas else None,
+                      "traffic_gb_per_launch": (traffic.get("eval_kernel<0,128>") or {}).get("gb"),
+                      "algorithmic_gb_per_launch": (M * prob.W * 8 + prob.n_pad * prob.n_pad + 8 * M) / 1e9},
+        "read_peaks_gbs": read_peaks,
+        "generation0": gen0,
+        "timed_population": pop_timed,
         "e1_replica": e1_rep,
         "lambda_sweep": lam_sweep,
         "configs": small_runs,

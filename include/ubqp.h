@@ -45,6 +45,8 @@ extern "C" {
 #define UBQP_ENOMEM -4  /* device allocation failed                                 */
 #define UBQP_EDEVICE -5 /* a HIP call or a kernel-side check failed (see last_error) */
 #define UBQP_EBUSY -6   /* serving: the waiting queue is at its limit; submit later  */
+#define UBQP_ELIMIT -7  /* an ascent to a local optimum reached the flip limit      */
+                        /* (ubqp_problem_set_flip_limit) and stopped short of it     */
 
 #define UBQP_MAX_N 8192
 #define UBQP_MAX_M (1ll << 22)
@@ -135,6 +137,22 @@ UBQP_API int ubqp_problem_create_typed(ubqp_ctx *ctx, int32_t n, const void *q_h
 UBQP_API int ubqp_problem_destroy(ubqp_problem *prob);
 /* n, padded size n_pad (a multiple of 128) and number of int8 planes (1 or 2). */
 UBQP_API int ubqp_problem_info(const ubqp_problem *prob, int32_t *n, int32_t *n_pad, int32_t *planes);
+/*
+ * Flip limit of the steepest ascent to a local optimum (max_flips = 0) on prob:
+ * `limit` >= 1 flips, or 0 for the default 64 n_pad + 4096.  In exact arithmetic
+ * the ascent always ends (every flip raises the integer f, which lies within
+ * +-sum |q_ij|), but that bound can exceed 10^9 flips, so a device-side limit
+ * keeps a runaway ascent from holding the GPU.  An ascent that reaches the limit
+ * stops there and the call that reports the device's checks -- ubqp_sync after
+ * ubqp_ascent or ubqp_relink, ubqp_run_result, ubqp_multistart,
+ * ubqp_batch_result, ubqp_sequential -- returns UBQP_ELIMIT, so a result cut
+ * short is never reported as a success.  (Served requests use the default; their
+ * status is UBQP_ELIMIT in that case.)  Capped ascents (max_flips > 0) stop at
+ * their cap without error, as the ascent's definition says.  Takes effect for
+ * ascents queued, and runs and batches created, after the call.
+ * Errors: UBQP_EINVAL (null prob, limit < 0).
+ */
+UBQP_API int ubqp_problem_set_flip_limit(ubqp_problem *prob, int32_t limit);
 
 /*
  * Glover diversification (Pseudocode section, "Diversify"; Glover 1998):
@@ -185,6 +203,14 @@ UBQP_API int ubqp_eval(ubqp_ctx *ctx, const ubqp_problem *prob, const uint64_t *
  * ubqp_eval_variant is ubqp_eval with an explicit variant.
  */
 UBQP_API int ubqp_tune_eval(ubqp_ctx *ctx, const ubqp_problem *prob, int64_t M, int32_t *variant, double *ms_host);
+/*
+ * Work of one ubqp_eval of M candidates on prob with the variant in force:
+ * *executed (may be NULL) receives the int8 matrix-core operations the launch
+ * executes (2 per multiply-add; the lower triangle by column tiles, K padded to
+ * the staging depth, whole row tiles), *dense (may be NULL) the dense definition
+ * 2 n^2 M per plane.  Host arithmetic only.  Errors: UBQP_EINVAL.
+ */
+UBQP_API int ubqp_eval_ops(const ubqp_problem *prob, int64_t M, double *executed, double *dense);
 UBQP_API int ubqp_eval_variant(ubqp_ctx *ctx, const ubqp_problem *prob, const uint64_t *X_d, int64_t M,
                                int64_t *f_d, int32_t variant);
 
@@ -195,6 +221,22 @@ UBQP_API int ubqp_eval_variant(ubqp_ctx *ctx, const ubqp_problem *prob, const ui
  * three timed launches after a warm-up.  Synchronous.
  */
 UBQP_API int ubqp_mfma_peak(ubqp_ctx *ctx, double *tops);
+
+/*
+ * Measurement: the read bandwidth (GB/s, 10^9 bytes) a streaming kernel sustains
+ * from a device buffer of `bytes` (a multiple of 4 KiB in [1 MiB, 64 GiB]) that
+ * the library allocates, fills and frees.  8 blocks of 256 threads per compute
+ * unit; block b reads `per_block` bytes (a multiple of 32 KiB) cycling through
+ * its window of `window` bytes (a multiple of 4 KiB dividing `bytes`) that starts
+ * at byte (b * window) mod bytes, in coalesced 16-byte loads, 8 in flight per
+ * thread.  window = bytes = a few MB: every block re-reads a buffer each XCD's L2
+ * holds.  bytes of about 100 MB with small windows: the XCD's concurrently
+ * running blocks cycle through more than its L2 holds, so the Infinity Cache
+ * serves the reads.  window = per_block, blocks * per_block = bytes >> 256 MB:
+ * every byte comes once from HBM.  Best of three timed launches after a warm-up.
+ * Synchronous.
+ */
+UBQP_API int ubqp_read_peak(ubqp_ctx *ctx, int64_t bytes, int64_t window, int64_t per_block, double *gbs);
 
 
 /*
@@ -217,10 +259,10 @@ UBQP_API int ubqp_screen(ubqp_ctx *ctx, const int64_t *f_d, int64_t M, int32_t l
  * the lowest index among equal maxima, while that Delta is > 0 and fewer than
  * max_flips flips were made (max_flips == 0: no cap).  In place: rows of X_d,
  * f_d[c] (in: f of the row, out: f after ascent) and flips_d[c] (int32, out).
- * Rows not listed are untouched.  Listed indices outside [0, M) are skipped.
- * Both that and an uncapped ascent exceeding the library's safety bound of
- * 64 n_pad + 4096 flips are reported as UBQP_EDEVICE by the next ubqp_sync
- * (or ubqp_multistart).
+ * Rows not listed are untouched.  Listed indices outside [0, M) are skipped and
+ * reported as UBQP_EDEVICE by the next ubqp_sync; an uncapped ascent that
+ * reaches the problem's flip limit (ubqp_problem_set_flip_limit) is reported as
+ * UBQP_ELIMIT by the next ubqp_sync.
  */
 UBQP_API int ubqp_ascent(ubqp_ctx *ctx, const ubqp_problem *prob, uint64_t *X_d, int64_t M, const int32_t *idx_d,
                 const int64_t *n_idx_d, int64_t max_idx, int64_t *f_d, int32_t max_flips,

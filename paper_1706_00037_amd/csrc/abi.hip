@@ -75,9 +75,11 @@ int ubqp_check_flag(ubqp_ctx *ctx)
     if (v) {
         hipLaunchKernelGGL(zero_i32, dim3(1), dim3(1), 0, ctx->stream, ctx->err_flag);
         UBQP_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-        return ubqp_fail(ctx, UBQP_EDEVICE, "%s",
-                         (v & 2) ? "an index outside its range was skipped (an ascent candidate or a relinking pair)"
-                                 : "ascent exceeded its safety bound of flips");
+        if (v & 2)
+            return ubqp_fail(ctx, UBQP_EDEVICE, "an index outside its range was skipped (an ascent candidate or a "
+                                                "relinking pair)%s", (v & 1) ? "; an ascent also reached its flip limit" : "");
+        return ubqp_fail(ctx, UBQP_ELIMIT, "an ascent to a local optimum reached the problem's flip limit and stopped "
+                                           "short of it (ubqp_problem_set_flip_limit)");
     }
     return UBQP_OK;
 }

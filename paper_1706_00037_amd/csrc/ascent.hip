@@ -731,7 +731,7 @@ AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, con
     a.f = f;
     a.flips = flips;
     a.max_flips = max_flips;
-    a.safety_cap = 64 * p->n_pad + 4096;
+    a.safety_cap = ubqp_problem_flip_limit(p);
     a.err = err_flag;
     return a;
 }

@@ -542,3 +542,19 @@ hipError_t ubqp_launch_eval_batch(hipStream_t st, int epilogue, const EvalArgs *
     }
     return hipGetLastError();
 }
+
+extern "C" int ubqp_eval_ops(const ubqp_problem *p, int64_t M, double *executed, double *dense)
+{
+    if (!p || M < 1 || M > UBQP_MAX_M) return UBQP_EINVAL;
+    const int KC = ubqp_eval_variant_kc(ubqp_eval_variant_for(p, M));
+    const int64_t rows = (M + BM - 1) / BM * BM;  // whole row tiles run their matrix ops
+    const int nk_full = (p->n_pad + KC - 1) / KC;
+    double macs = 0.0;
+    for (int nt = 0; nt < p->n_pad / BN; nt++) {
+        const int nk = min(nk_full, (nt * BN + BN + KC - 1) / KC);  // lower triangle: K over [0, n0 + BN)
+        macs += (double)BN * nk * KC;
+    }
+    if (executed) *executed = 2.0 * macs * (double)rows * p->planes;
+    if (dense) *dense = 2.0 * (double)p->n * p->n * (double)M * p->planes;
+    return UBQP_OK;
+}

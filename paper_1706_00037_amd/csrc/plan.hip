@@ -313,7 +313,6 @@ int plan_create(ubqp_ctx *ctx, int count, const ubqp_problem *const *probs, cons
         r.pr = params[i];
         r.L = ubqp_inst_layout(probs[i], &params[i]);
         r.dump = dumps ? dumps[i] : nullptr;
-        r.err = ctx->err_flag;
         pl->inst.push_back(r);
         base.push_back(total);
         total += r.L.total;
@@ -323,7 +322,18 @@ int plan_create(ubqp_ctx *ctx, int count, const ubqp_problem *const *probs, cons
         plan_free(pl);
         return ubqp_hip_fail(ctx, e, "multistart state");
     }
-    for (int i = 0; i < count; i++) pl->inst[(size_t)i].base = pl->state + base[(size_t)i];
+    for (int i = 0; i < count; i++) {
+        // each instance reports its ascent's checks to a flag of its own, so a result
+        // names the instance whose ascent failed
+        InstRef &r = pl->inst[(size_t)i];
+        r.base = pl->state + base[(size_t)i];
+        r.err = r.at<int32_t>(r.L.err);
+        if (e == hipSuccess) e = ubqp_queue_zero(ctx->stream, r.err, 1);
+    }
+    if (e != hipSuccess) {
+        plan_free(pl);
+        return ubqp_hip_fail(ctx, e, "error flags");
+    }
     pl->t.build(pl->inst);
     e = hipMalloc(&pl->tables, std::max<size_t>(pl->t.host.size(), 256));
     if (e == hipSuccess) e = hipMemcpy(pl->tables, pl->t.host.data(), pl->t.host.size(), hipMemcpyHostToDevice);
@@ -399,7 +409,9 @@ int plan_result(ubqp_plan *pl, int i, ubqp_result *res)
     hipStream_t st = ctx->stream;
     const InstRef &r = pl->inst[(size_t)i];
     ubqp_scal hs;
+    int32_t errv = 0;
     UBQP_HIP_TRY(ctx, hipMemcpyAsync(&hs, r.at<ubqp_scal>(r.L.scal), sizeof hs, hipMemcpyDeviceToHost, st));
+    UBQP_HIP_TRY(ctx, hipMemcpyAsync(&errv, r.err, sizeof errv, hipMemcpyDeviceToHost, st));
     if (res->best_x_host)
         UBQP_HIP_TRY(ctx, hipMemcpyAsync(res->best_x_host, r.at<uint64_t>(r.L.bestx), (size_t)r.p->W * 8,
                                          hipMemcpyDeviceToHost, st));
@@ -407,7 +419,12 @@ int plan_result(ubqp_plan *pl, int i, ubqp_result *res)
         UBQP_HIP_TRY(ctx, hipMemcpyAsync(res->stats_host, r.at<int64_t>(r.L.stats), (size_t)pl->g * 5 * 8,
                                          hipMemcpyDeviceToHost, st));
     UBQP_HIP_TRY(ctx, hipStreamSynchronize(st));
-    UBQP_TRY(ubqp_check_flag(ctx));
+    // the flag stays set: every later generation builds on the cut-short ascent
+    if (errv & 2) return ubqp_fail(ctx, UBQP_EDEVICE, "instance %d: an ascent candidate index was out of range", i);
+    if (errv & 1)
+        return ubqp_fail(ctx, UBQP_ELIMIT, "instance %d: an ascent to a local optimum reached the problem's flip "
+                                           "limit of %d flips and stopped short of it", i,
+                         ubqp_problem_flip_limit(r.p));
     if (res->gen_ms_host)
         for (int32_t g = 0; g < pl->g; g++) {
             float ms = 0.f;

@@ -270,4 +270,17 @@ int ubqp_problem_info(const ubqp_problem *p, int32_t *n, int32_t *n_pad, int32_t
     return UBQP_OK;
 }
 
+int ubqp_problem_set_flip_limit(ubqp_problem *p, int32_t limit)
+{
+    if (!p) return UBQP_EINVAL;
+    if (limit < 0) return ubqp_fail(p->ctx, UBQP_EINVAL, "flip limit %d < 0", limit);
+    p->flip_limit = limit;
+    return UBQP_OK;
+}
+
 }  // extern "C"
+
+int32_t ubqp_problem_flip_limit(const ubqp_problem *p)
+{
+    return p->flip_limit > 0 ? p->flip_limit : 64 * p->n_pad + 4096;
+}

@@ -340,7 +340,7 @@ hipError_t poll_finishing(ubqp_server *s)
             std::lock_guard<std::mutex> lk(s->m);
             release(s, r);
         }
-        publish(s, r, errv ? UBQP_EDEVICE : UBQP_OK, &sc.best_f, sc.have_best);
+        publish(s, r, (errv & 2) ? UBQP_EDEVICE : (errv & 1) ? UBQP_ELIMIT : UBQP_OK, &sc.best_f, sc.have_best);
     }
     return hipSuccess;
 }

@@ -27,7 +27,7 @@ struct ubqp_ctx {
     enum Slot { WS_PARTIALS, WS_Y, WS_STAGE, WS_TUNE, WS_RELINK, WS_COUNT };
     void *ws[WS_COUNT] = {};
     size_t ws_bytes[WS_COUNT] = {};
-    int32_t *err_flag = nullptr;  // device int32: kernel-side checks (ascent safety cap)
+    int32_t *err_flag = nullptr;  // device int32: kernel-side checks (bit 0: flip limit, bit 1: index skipped)
 };
 
 struct ubqp_problem {
@@ -41,7 +41,10 @@ struct ubqp_problem {
     uint64_t *deriv_x = nullptr;  // [W] first-derivative starting solution
     int64_t weight0 = 1;       // weight of plane 0 (256 when split)
     int64_t bias = 0;          // 128 when split: f += bias * popcount(x)^2, y_i += bias * popcount(x)
+    int32_t flip_limit = 0;    // flips an uncapped ascent may make before it stops with UBQP_ELIMIT (0: default)
 };
+// The flip limit in force for p: its own, or 64 n_pad + 4096.
+int32_t ubqp_problem_flip_limit(const ubqp_problem *p);
 
 // Small device scalars of a multistart run.
 struct ubqp_scal {
@@ -308,7 +311,7 @@ hipError_t ubqp_launch_screen(hipStream_t st, const ScreenArgs &a);
 hipError_t ubqp_launch_screen_batch(hipStream_t st, const ScreenArgs *args, const int64_t *prefix, int count,
                                     int64_t blocks);
 
-// err_flag |= 1: safety cap reached; |= 2: an index outside [0, x_rows) was skipped.
+// err_flag |= 1: an uncapped ascent reached the flip limit; |= 2: an index outside [0, x_rows) was skipped.
 // Ascends X[idx[offset + r]] for r < min(*nidx_d - offset, cap), starting from Y rows r.
 AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, const int32_t *idx, const int64_t *nidx_d,
                          int64_t offset, int64_t cap, const int32_t *Y, int64_t *f, int32_t max_flips, int32_t *flips,

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libubqp.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ubqp.h")
 
 UBQP_OK, UBQP_EINVAL, UBQP_ERANGE, UBQP_EASYM, UBQP_ENOMEM, UBQP_EDEVICE, UBQP_EBUSY = 0, -1, -2, -3, -4, -5, -6
+UBQP_ELIMIT = -7
 UBQP_DERIV_START, UBQP_TIMING, UBQP_NO_GRAPH, UBQP_AUTOTUNE, UBQP_BLEND = 1, 2, 4, 8, 16
 UBQP_EVAL_VARIANTS = 6
 UBQP_FMT_ORLIB, UBQP_FMT_TRIPLETS = 1, 2
@@ -90,10 +91,13 @@ def load():
         "ubqp_problem_create_typed": [P, i32, P, i32, ctypes.POINTER(P)],
         "ubqp_problem_destroy": [P],
         "ubqp_problem_info": [P, P, P, P],
+        "ubqp_problem_set_flip_limit": [P, i32],
         "ubqp_diversify": [P, i32, P, i64, i32, P, i64],
         "ubqp_blend": [P, i32, P, i64, i64, i64, u64, P],
         "ubqp_sequential": [P, P, P, P],
         "ubqp_mfma_peak": [P, P],
+        "ubqp_read_peak": [P, i64, i64, i64, P],
+        "ubqp_eval_ops": [P, i64, P, P],
         "ubqp_relink": [P, P, P, i64, P, i64, i32, P, P, P, P],
         "ubqp_eval": [P, P, P, i64, P],
         "ubqp_eval_variant": [P, P, P, i64, P, i32],
@@ -198,6 +202,11 @@ class Problem:
         n_, npad, planes = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         ctx._call("ubqp_problem_info", h, ctypes.byref(n_), ctypes.byref(npad), ctypes.byref(planes))
         self.n_pad, self.planes = npad.value, planes.value
+
+    def set_flip_limit(self, limit: int):
+        """Flips an ascent to a local optimum may make on this problem before it stops
+        and reports UBQP_ELIMIT (0: the default 64 n_pad + 4096)."""
+        self.ctx._call("ubqp_problem_set_flip_limit", self.h, int(limit))
 
     def close(self):
         if self.h is not None:
@@ -564,6 +573,22 @@ class Context:
         self.sync()
         return dict(pairs=pairs, X=X.cpu().numpy().view(np.uint64), f_mid=fm.cpu().numpy(), f_out=fo.cpu().numpy(),
                     steps=st.cpu().numpy())
+
+    def eval_ops(self, prob: Problem, M: int):
+        """(executed, dense) int8 matrix-core operations of one evaluation of M
+        candidates on prob (ubqp_eval_ops)."""
+        ex, de = ctypes.c_double(), ctypes.c_double()
+        rc = self.L.ubqp_eval_ops(prob.h, int(M), ctypes.byref(ex), ctypes.byref(de))
+        if rc != UBQP_OK:
+            raise UbqpError(rc, "ubqp_eval_ops")
+        return float(ex.value), float(de.value)
+
+    def read_peak(self, nbytes: int, window: int, per_block: int) -> float:
+        """Read bandwidth in GB/s of a streaming kernel over a buffer of nbytes, each
+        block cycling through a window (ubqp_read_peak)."""
+        v = ctypes.c_double()
+        self._call("ubqp_read_peak", self.h, int(nbytes), int(window), int(per_block), ctypes.byref(v))
+        return float(v.value)
 
     def mfma_peak(self) -> float:
         """Sustained int8 matrix-core rate of the device in TOP/s (ubqp_mfma_peak)."""

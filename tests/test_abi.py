@@ -91,3 +91,8 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_flip_limit_rejects_null_problem_without_a_device():
+    L = ubqp.load()
+    assert L.ubqp_problem_set_flip_limit(None, 5) == ubqp.UBQP_EINVAL
