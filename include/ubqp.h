@@ -251,6 +251,21 @@ UBQP_API int ubqp_screen(ubqp_ctx *ctx, const int64_t *f_d, int64_t M, int32_t l
                 int32_t *pass_idx_d, int64_t *n_pass_d, int64_t *sum_max_d);
 
 /*
+ * ubqp_screen for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, layout and results as ubqp_screen, but the block partials live in a
+ * static device array of the library (48 KiB per GPU, held until the process
+ * ends) instead of the context's growable workspace, so the call allocates
+ * nothing.  M must be at most UBQP_SCREEN_NOALLOC_MAX_M (else UBQP_EINVAL, nothing
+ * launched).  Every call on one GPU shares that GPU's array: calls that overlap on
+ * one GPU (other streams, other contexts, other threads) race and give wrong
+ * results; calls ordered on one stream are safe.
+ */
+#define UBQP_SCREEN_NOALLOC_MAX_M (1ll << 22)
+UBQP_API int ubqp_screen_noalloc(ubqp_ctx *ctx, const int64_t *f_d, int64_t M, int32_t lam_num, int32_t lam_den,
+                                 int32_t *pass_idx_d, int64_t *n_pass_d, int64_t *sum_max_d);
+
+/*
  * Steepest 1-flip ascent (Pseudocode section; deltas of Glover et al. 2002) of
  * the candidates X_d[idx_d[p]], p < *n_idx_d (device count, at most max_idx);
  * X_d, f_d and flips_d have M rows:

@@ -115,7 +115,7 @@ int ubqp_create(ubqp_ctx **out, int device, void *stream)
         return UBQP_EDEVICE;
     }
     hipLaunchKernelGGL(zero_i32, dim3(1), dim3(1), 0, ctx->stream, ctx->err_flag);
-    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess || ubqp_screen_scratch_init(ctx) != UBQP_OK) {
         (void)hipFree(ctx->err_flag);
         delete ctx;
         return UBQP_EDEVICE;

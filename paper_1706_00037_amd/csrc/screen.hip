@@ -6,6 +6,8 @@
 // Three HBM-bound passes over f (8 B/candidate each): block partial Sum/Max,
 // per-block passer counts, and an order-preserving scatter.  No atomics, so the
 // output is the same on every run.
+#include <mutex>
+
 #include "ubqp_internal.h"
 
 namespace {
@@ -253,4 +255,56 @@ hipError_t ubqp_launch_screen_batch(hipStream_t st, const ScreenArgs *args, cons
     hipLaunchKernelGGL(screen_count_b, dim3((unsigned)blocks), dim3(THR), 0, st, args, prefix, count);
     hipLaunchKernelGGL(screen_scatter_b, dim3((unsigned)blocks), dim3(THR), 0, st, args, prefix, count);
     return hipGetLastError();
+}
+
+// ---- screening without allocation ----------------------------------------------
+// The block partials of ubqp_screen_noalloc live in one file-scope device array per
+// GPU.  Host code never passes the array's name to a kernel (on the host it is only
+// a stand-in): the device address of each GPU's copy is looked up once, with that
+// GPU current, when the first context on it is created, and kept per device.
+static constexpr int64_t STATIC_BLOCKS = (UBQP_SCREEN_NOALLOC_MAX_M + CH - 1) / CH;
+static __device__ __align__(256) int64_t scratch[3 * STATIC_BLOCKS];  // psum, pmax, cnt: 48 KiB
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES] = {};
+
+}  // namespace
+
+int ubqp_screen_scratch_init(ubqp_ctx *ctx)
+{
+    if (ctx->device < 0 || ctx->device >= MAX_DEVICES)
+        return ubqp_fail(ctx, UBQP_EDEVICE, "device %d beyond the %d the static screen scratch tracks", ctx->device,
+                         MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_ptr[ctx->device]) return UBQP_OK;
+    void *ptr = nullptr;
+    UBQP_HIP_TRY(ctx, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return ubqp_fail(ctx, UBQP_EDEVICE, "hipGetSymbolAddress returned a null address for the screen scratch");
+    scratch_ptr[ctx->device] = ptr;
+    return UBQP_OK;
+}
+
+extern "C" int ubqp_screen_noalloc(ubqp_ctx *ctx, const int64_t *f_d, int64_t M, int32_t lam_num, int32_t lam_den,
+                                   int32_t *pass_idx_d, int64_t *n_pass_d, int64_t *sum_max_d)
+{
+    if (!ctx || !f_d || !pass_idx_d || !n_pass_d || !sum_max_d) return ubqp_fail(ctx, UBQP_EINVAL, "null argument");
+    if (M < 1 || M > UBQP_SCREEN_NOALLOC_MAX_M)
+        return ubqp_fail(ctx, UBQP_EINVAL, "M=%lld outside [1, %lld], the size of the static screen scratch",
+                         (long long)M, (long long)UBQP_SCREEN_NOALLOC_MAX_M);
+    if (lam_den < 1 || lam_num < 0 || lam_num > lam_den)
+        return ubqp_fail(ctx, UBQP_EINVAL, "lambda=%d/%d outside [0, 1]", lam_num, lam_den);
+    UBQP_TRY(ubqp_set_device(ctx));
+    void *part = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(scratch_mu);
+        if (ctx->device >= 0 && ctx->device < MAX_DEVICES) part = scratch_ptr[ctx->device];
+    }
+    if (!part) return ubqp_fail(ctx, UBQP_EDEVICE, "the static screen scratch of device %d was not set up", ctx->device);
+    // every partial is written (reduce: psum, pmax; count: cnt) before it is read
+    UBQP_HIP_TRY(ctx, ubqp_launch_screen(ctx->stream, ubqp_screen_args(f_d, M, lam_num, lam_den, pass_idx_d, n_pass_d,
+                                                                       sum_max_d, part)));
+    return UBQP_OK;
 }

@@ -308,6 +308,9 @@ hipError_t ubqp_launch_order_batch(hipStream_t st, const OrdArgs *args, int coun
 ScreenArgs ubqp_screen_args(const int64_t *f, int64_t M, int32_t lam_num, int32_t lam_den, int32_t *idx,
                             int64_t *npass, int64_t *sum_max, void *partials);
 hipError_t ubqp_launch_screen(hipStream_t st, const ScreenArgs &a);
+// Look up (once per device, with ctx->device current) the device address of the
+// static scratch behind ubqp_screen_noalloc.
+int ubqp_screen_scratch_init(ubqp_ctx *ctx);
 hipError_t ubqp_launch_screen_batch(hipStream_t st, const ScreenArgs *args, const int64_t *prefix, int count,
                                     int64_t blocks);
 

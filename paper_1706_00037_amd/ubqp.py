@@ -26,6 +26,7 @@ UBQP_EVAL_VARIANTS = 6
 UBQP_FMT_ORLIB, UBQP_FMT_TRIPLETS = 1, 2
 PHASES = ("diversify", "eval", "screen", "ascent", "select", "ascent_kernel")  # the last is a part of "ascent"
 MAX_N, MAX_M, MAX_H = 8192, 1 << 22, 256
+UBQP_SCREEN_NOALLOC_MAX_M = 1 << 22
 INT64_MIN = -(1 << 63)
 
 _lib = None
@@ -103,6 +104,7 @@ def load():
         "ubqp_eval_variant": [P, P, P, i64, P, i32],
         "ubqp_tune_eval": [P, P, i64, ctypes.POINTER(i32), P],
         "ubqp_screen": [P, P, i64, i32, i32, P, P, P],
+        "ubqp_screen_noalloc": [P, P, i64, i32, i32, P, P, P],
         "ubqp_ascent": [P, P, P, i64, P, P, i64, P, i32, P],
         "ubqp_multistart": [P, P, ctypes.POINTER(Params), P, ctypes.POINTER(Result)],
         "ubqp_run_create": [P, P, ctypes.POINTER(Params), P, ctypes.POINTER(P)],
@@ -484,6 +486,15 @@ class Context:
         torch = self.torch
         M = f.numel() if M is None else M
         self._call("ubqp_screen", self.h, self._t(f, torch.int64, M, "f"), M, lam_num, lam_den,
+                   self._t(idx, torch.int32, M, "idx"), self._t(npass, torch.int64, 1, "npass"),
+                   self._t(sum_max, torch.int64, 2, "sum_max"))
+
+    def screen_noalloc(self, f, lam_num, lam_den, idx, npass, sum_max, M=None):
+        """ubqp_screen_noalloc: the screen with its partials in the library's static
+        device scratch (no allocation; calls overlapping on one GPU race)."""
+        torch = self.torch
+        M = f.numel() if M is None else M
+        self._call("ubqp_screen_noalloc", self.h, self._t(f, torch.int64, M, "f"), M, lam_num, lam_den,
                    self._t(idx, torch.int32, M, "idx"), self._t(npass, torch.int64, 1, "npass"),
                    self._t(sum_max, torch.int64, 2, "sum_max"))
 
