@@ -450,6 +450,7 @@ __global__ __launch_bounds__(64, AscOcc<NB>::waves) void ascent_i8_kernel(AscArg
     const int lane = threadIdx.x;
     int64_t P = *a.nidx_d - a.offset;
     P = P < a.max_idx ? P : a.max_idx;
+    if (P <= a.team_max) return;  // the team kernel of the same launch takes these passers
     for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_i8<NB>(a, p, lane);
 }
 
@@ -480,7 +481,168 @@ __global__ __launch_bounds__(64, AscOcc<NB>::waves) void ascent_i8_batched(const
     const int64_t w0 = blockIdx.x - prefix[i], nw = prefix[i + 1] - prefix[i];
     int64_t P = *a.nidx_d - a.offset;
     P = P < a.max_idx ? P : a.max_idx;
+    if (P <= a.team_max) return;  // the team kernel of the same launch takes these passers
     for (int64_t p = w0; p < P; p += nw) ascend_i8<NB>(a, p, threadIdx.x);
+}
+
+// ---- team ascent: few passers, four waves each ----------------------------------
+// A launch with at most UBQP_TEAM_MAX_P passers leaves most SIMDs idle, and each
+// passer's flip chain (a row read, then the update and argmax of all its columns
+// by one wave) is the launch's critical path.  There four waves share a passer:
+// virtual lane v = 64 w + l of wave w owns the columns [v PLT, (v+1) PLT),
+// PLT = 16 NBT, a quarter of the one-wave range, so each wave reads a quarter of
+// the row and updates a quarter of the keys.  The waves combine their best
+// (Delta, column) through LDS with one barrier per flip; since wave w's columns
+// precede wave w+1's, the lowest wave attaining the largest Delta holds the
+// lowest such column.  The keys and signs are those of the one-wave ascent, with
+// the key's tie-break part rewritten for the shorter lane range.
+template <int NBT>
+__device__ void ascend_i8_team(const AscArgs &a, int64_t p, int w, int lane, int2 (*slots)[UBQP_TEAM])
+{
+    constexpr int PLT = 16 * NBT;
+    const int v = w * 64 + lane;
+    const int64_t c = a.idx[a.offset + p];
+    if (c < 0 || c >= a.x_rows) {
+        if (w == 0 && lane == 0) atomicOr(a.err, 2);
+        return;  // uniform over the team: every wave reads the same index
+    }
+    uint64_t *xr = a.X + c * a.W;
+    v16i kk[NBT];
+    uint32_t ss[NBT][4];
+#pragma unroll
+    for (int b = 0; b < NBT; b++) {
+        const int col0 = v * PLT + 16 * b;
+        const bool in = col0 < a.n_pad;
+        const int32_t *yrow = a.Y + p * a.n_pad + col0;
+#pragma unroll
+        for (int t4 = 0; t4 < 4; t4++) {
+            int4 y = {0, 0, 0, 0};
+            if (in) y = ubqp_ldg16i(yrow + 4 * t4);
+            const int32_t kv[4] = {y.x, y.y, y.z, y.w};
+            uint32_t sw = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int t = 4 * t4 + k;
+                // Delta * 256 and x from the key, the tie-break part for this lane's range
+                const int32_t key = (in ? (kv[k] & (int32_t)0xFFFFFF01) : 0) | (2 * (127 - (16 * b + t)));
+                kk[b][t] = key;
+                sw |= ((key & 1) ? 0xFFu : 0x01u) << (8 * k);
+            }
+            ss[b][t4] = sw;
+        }
+    }
+    const int8_t *qa = (const int8_t *)a.qa;
+    int64_t gain = 0;
+    int32_t flips = 0;
+    const int32_t cap = a.max_flips > 0 ? a.max_flips : a.safety_cap;
+    int32_t V;
+    int par = 0;
+    __builtin_amdgcn_s_waitcnt(WAIT_VM_LGKM_0);
+    for (;;) {
+        const int32_t best = lane_max<NBT>(kk);
+        const int32_t ld = best >> 8;
+        const int32_t Vw = wave_max_i32(ld);
+        const int lw = __ffsll((unsigned long long)__ballot(ld == Vw)) - 1;
+        const int32_t bw = __builtin_amdgcn_readlane(best, lw);
+        if (lane == 0) {
+            const int localw = 127 - ((bw >> 1) & 127);
+            slots[par][w] = int2{Vw, ((w * 64 + lw) * PLT + localw) | ((bw & 1) << 30)};
+        }
+        __syncthreads();
+        int2 win = slots[par][0];
+#pragma unroll
+        for (int u = 1; u < UBQP_TEAM; u++) {
+            const int2 o = slots[par][u];
+            win = o.x > win.x ? o : win;  // strict: the lowest wave wins ties
+        }
+        par ^= 1;  // the other slot set next flip: no second barrier needed
+        V = win.x;
+        if (V <= 0 || flips >= cap) break;
+        const int K = win.y & 0x3FFFFFFF;
+        const int32_t xk = (win.y >> 30) & 1;
+        const int vk = K / PLT, local = K - vk * PLT;
+        const int bs = local >> 4, ts = local & 15;
+        const bool own = v == vk;
+        const int32_t knew = -V * 256 + 2 * (127 - local) + (1 - xk);
+        const uint32_t sflip = own ? 0xFEu << (8 * (ts & 3)) : 0u;
+#pragma unroll
+        for (int b = 0; b < NBT; b++) {
+            if (b == bs) {
+                const int32_t ko = kk[b][ts];
+                kk[b][ts] = own ? knew : ko;
+#pragma unroll
+                for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts >> 2)) ? sflip : 0u;
+            }
+        }
+        gain += V;
+        flips++;
+        const int32_t step = xk ? -512 : 512;
+        const int8_t *row = qa + (int64_t)K * a.ncol_a;
+        uint4 wr[NBT];
+#pragma unroll
+        for (int b = 0; b < NBT; b++) {
+            const int col0 = v * PLT + 16 * b;
+            wr[b] = col0 < a.ncol_a ? ubqp_ldg16(row + col0) : uint4{0u, 0u, 0u, 0u};
+        }
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int b = 0; b < NBT; b++) {
+            int32_t k[16];
+#pragma unroll
+            for (int t = 0; t < 16; t++) k[t] = kk[b][t];
+            update_keys8(k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], wr[b].x, wr[b].y, ss[b][0], ss[b][1], step);
+            update_keys8(k[8], k[9], k[10], k[11], k[12], k[13], k[14], k[15], wr[b].z, wr[b].w, ss[b][2], ss[b][3],
+                         step);
+#pragma unroll
+            for (int t = 0; t < 16; t++) kk[b][t] = k[t];
+        }
+        __builtin_amdgcn_s_setprio(0);
+    }
+    if (V > 0 && a.max_flips == 0 && w == 0 && lane == 0) atomicOr(a.err, 1);  // flip limit reached
+#pragma unroll
+    for (int b = 0; b < NBT; b++) {
+        uint32_t bits = 0;
+#pragma unroll
+        for (int t = 0; t < 16; t++) bits |= ((uint32_t)kk[b][t] & 1u) << t;
+        const int ci = (v * PLT + 16 * b) >> 4;
+        if (ci < 4 * a.W) ((uint16_t *)xr)[ci] = (uint16_t)bits;
+    }
+    if (w == 0 && lane == 0) {
+        a.f[c] += gain;
+        a.flips[c] = flips;
+    }
+    // the next passer's first flip writes slot set 0, which slower waves of the team
+    // may still be reading in this passer's last flip
+    __syncthreads();
+}
+
+// Team kernels: one workgroup of UBQP_TEAM waves per passer.  They run only when
+// the launch's passer count is at most UBQP_TEAM_MAX_P (the one-wave kernels take
+// the other launches and return at once here, and the other way round).
+template <int NBT>
+__global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_i8_team_kernel(AscArgs a)
+{
+    __shared__ int2 slots[2][UBQP_TEAM];
+    int64_t P = *a.nidx_d - a.offset;
+    P = P < a.max_idx ? P : a.max_idx;
+    if (P > a.team_max) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_i8_team<NBT>(a, p, w, lane, slots);
+}
+
+template <int NBT>
+__global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_i8_team_batched(const AscArgs *args, const int64_t *prefix,
+                                                                          int count)
+{
+    __shared__ int2 slots[2][UBQP_TEAM];
+    const int i = ubqp_find_inst(prefix, count, blockIdx.x);
+    const AscArgs a = args[i];
+    const int64_t b0 = blockIdx.x - prefix[i], nb = prefix[i + 1] - prefix[i];
+    int64_t P = *a.nidx_d - a.offset;
+    P = P < a.max_idx ? P : a.max_idx;
+    if (P > a.team_max) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t p = b0; p < P; p += nb) ascend_i8_team<NBT>(a, p, w, lane, slots);
 }
 
 // ---- greedy path relinking -------------------------------------------------
@@ -733,7 +895,27 @@ AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, con
     a.max_flips = max_flips;
     a.safety_cap = ubqp_problem_flip_limit(p);
     a.err = err_flag;
+    // one plane and at least four 16-column blocks per one-wave lane: launches with
+    // few passers ascend them in teams of waves
+    a.team_max = (p->planes == 1 && (p->n_pad + 1023) / 1024 >= UBQP_TEAM_MIN_NB) ? UBQP_TEAM_MAX_P : 0;
     return a;
+}
+
+int64_t ubqp_ascent_team_blocks(const AscArgs &a)
+{
+    if (a.team_max <= 0) return 0;
+    return a.max_idx < a.team_max ? (a.max_idx < 1 ? 1 : a.max_idx) : a.team_max;
+}
+
+static hipError_t launch_team(hipStream_t st, const AscArgs &a)
+{
+    const unsigned blocks = (unsigned)ubqp_ascent_team_blocks(a);
+    if (blocks == 0) return hipSuccess;
+    if ((a.n_pad + 4095) / 4096 <= 1)
+        hipLaunchKernelGGL(ascent_i8_team_kernel<1>, dim3(blocks), dim3(64 * UBQP_TEAM), 0, st, a);
+    else
+        hipLaunchKernelGGL(ascent_i8_team_kernel<2>, dim3(blocks), dim3(64 * UBQP_TEAM), 0, st, a);
+    return hipGetLastError();
 }
 
 int ubqp_ascent_nb(const AscArgs &a) { return (a.n_pad + 1023) / 1024; }
@@ -741,6 +923,8 @@ int64_t ubqp_ascent_waves(const AscArgs &a) { return a.max_idx < 8192 ? (a.max_i
 
 hipError_t ubqp_launch_ascent(hipStream_t st, const AscArgs &a)
 {
+    hipError_t e = launch_team(st, a);
+    if (e != hipSuccess) return e;
     const unsigned waves = (unsigned)ubqp_ascent_waves(a);
 #define L16(NB) hipLaunchKernelGGL(ascent_i16_kernel<NB>, dim3(waves), dim3(64), 0, st, a)
 #define L8(NB) hipLaunchKernelGGL(ascent_i8_kernel<NB>, dim3(waves), dim3(64), 0, st, a)
@@ -751,6 +935,19 @@ hipError_t ubqp_launch_ascent(hipStream_t st, const AscArgs &a)
     }
 #undef L16
 #undef L8
+    return hipGetLastError();
+}
+
+hipError_t ubqp_launch_ascent_team_batch(hipStream_t st, int n_pad_max, const AscArgs *args, const int64_t *prefix,
+                                         int count, int64_t blocks)
+{
+    if (blocks <= 0) return hipSuccess;
+    if ((n_pad_max + 4095) / 4096 <= 1)
+        hipLaunchKernelGGL(ascent_i8_team_batched<1>, dim3((unsigned)blocks), dim3(64 * UBQP_TEAM), 0, st, args, prefix,
+                           count);
+    else
+        hipLaunchKernelGGL(ascent_i8_team_batched<2>, dim3((unsigned)blocks), dim3(64 * UBQP_TEAM), 0, st, args, prefix,
+                           count);
     return hipGetLastError();
 }
 

@@ -36,9 +36,19 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 256, BN = 128, THR = 256;
-constexpr int WM = 64;            // wave tile: the four waves split the 256 rows, each covers all 128 columns
-constexpr int FM = WM / 32, FN = BN / 32;
+constexpr int BM = 256, THR = 256;  // workgroup rows (one staged X row per thread)
+
+// Workgroup tile geometry: BM x BN, the four waves arranged WR x WC, each wave
+// WTM x WTN = (BM / WR) x (BN / WC) in 32 x 32 MFMA blocks.  In use: BN = 128, WR = 4,
+// waves of 64 x 128 (two workgroups per CU for KC <= 128).  The body also accepts
+// BN = 256 (waves of 64 x 256 or 128 x 128: column tiles may reach past n_pad),
+// which was measured slower.
+template <int BN_, int WR_> struct Geom {
+    static constexpr int BN = BN_, WR = WR_, WC = 4 / WR_;
+    static constexpr int WTM = BM / WR, WTN = BN / WC;
+    static constexpr int FM = WTM / 32, FN = WTN / 32;
+    static_assert(WR * WC == 4 && (WTN == 128 || WTN == 256), "four waves, 128 or 256 columns per wave");
+};
 
 // 16 bits -> 16 bytes of 0/1: nibble v spreads to bytes by v * 0x00204081
 // (bit i lands at 8i, no carries because the copies are 7 bits apart).
@@ -71,6 +81,8 @@ enum { EPI_ROWDOT = 0, EPI_Y = 1, EPI_KEYS = 2 };
 #define SG_MFMA 0x008
 #define SG_DSR 0x100
 
+__device__ inline int word0_of(int col) { return col >> 6; }
+
 // Consecutive workgroups go round-robin to the 8 XCDs: give each XCD a
 // contiguous run of tiles, a bijection on [0, total).  Tiles are numbered
 // n-tile-major, so the workgroups resident on one XCD share a Q column block in
@@ -81,9 +93,14 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t total)
     return xcd * per + (xcd < rem ? xcd : rem) + j;
 }
 
-template <int EPI, int KC>
+template <int EPI, int KC, int BN_, int WR_>
 __device__ void eval_body(const EvalArgs &a, int64_t tile)
 {
+    using GM = Geom<BN_, WR_>;
+    constexpr int BN = GM::BN, WC = GM::WC, WTM = GM::WTM, WTN = GM::WTN, FM = GM::FM, FN = GM::FN;
+    // a column tile wider than the padding granularity can reach past n_pad: its
+    // Q rows there read as zero and the waves whose columns lie there store nothing
+    constexpr bool ROWGUARD = BN > UBQP_NPAD_ALIGN;
     constexpr bool STORE_Y = EPI != EPI_ROWDOT;
     // The objective needs only the lower triangle of the symmetric Q:
     //     f = sum_j x_j (2 acc_j - q_jj),   acc_j = sum_{i <= j} q_ij x_i,
@@ -99,6 +116,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     __shared__ __align__(16) uint64_t As[2][BM * APITCH];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WC, wc = wave % WC;
     const int64_t T = (int64_t)a.m_tiles * a.n_tiles;
     const int plane = (int)(tile / T);
     const int64_t t = tile - plane * T;
@@ -135,15 +153,19 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
 
     uint64_t aw[KC / 64];
     uint4 br[BCH];
-    // Key epilogue with KC = BN: the X words of this tile's columns pass through the
-    // staging registers at the K step kc = n0 / KC; a copy goes to LDS after the
-    // loop for the epilogue (the same gathered rows, zero where the staging is zero).
-    constexpr bool KEYS_LDS = EPI == EPI_KEYS && KC == BN;
-    uint64_t xt[KC / 64] = {};
+    // Key epilogue with KC dividing BN: the X words of this tile's columns pass
+    // through the staging registers at the K steps kc = n0 / KC + s; a copy goes to
+    // LDS after the loop for the epilogue (the same gathered rows, zero where the
+    // staging is zero).
+    constexpr bool KEYS_LDS = EPI == EPI_KEYS && KC <= BN && BN % KC == 0;
+    uint64_t xt[BN / 64] = {};
     int32_t dg[FN] = {};  // key epilogue: q_jj of the lane's columns, loaded early
     if constexpr (EPI == EPI_KEYS) {
 #pragma unroll
-        for (int ni = 0; ni < FN; ni++) dg[ni] = a.diag[n0 + ni * 32 + (tid & 31)];
+        for (int ni = 0; ni < FN; ni++) {
+            const int col = n0 + wc * WTN + ni * 32 + (tid & 31);
+            dg[ni] = col < a.n_pad ? a.diag[col] : 0;
+        }
     }
     const int nk_full = (a.n_pad + KC - 1) / KC;
     const int nk = TRI ? min(nk_full, (n0 + BN + KC - 1) / KC) : nk_full;
@@ -154,13 +176,19 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
             const int wi_ = (kc) * (KC / 64) + w_;                                            \
             aw[w_] = (xrow && wi_ < a.W) ? ubqp_ldg8(xrow + wi_) : 0ull;                      \
         }                                                                                     \
-        if (KEYS_LDS && (kc) * KC == n0) {                                                    \
-            _Pragma("unroll") for (int w_ = 0; w_ < KC / 64; w_++) xt[w_] = aw[w_];           \
+        if (KEYS_LDS) {                                                                       \
+            _Pragma("unroll") for (int s_ = 0; s_ < BN / KC; s_++) {                          \
+                if ((kc) * KC == n0 + s_ * KC) {                                              \
+                    _Pragma("unroll") for (int w_ = 0; w_ < KC / 64; w_++)                    \
+                        xt[s_ * (KC / 64) + w_] = aw[w_];                                     \
+                }                                                                             \
+            }                                                                                 \
         }                                                                                     \
         const bool kin_ = (kc) * KC + bc16 * 16 < a.n_pad;                                    \
         _Pragma("unroll") for (int i_ = 0; i_ < BCH; i_++) {                                  \
-            br[i_] = kin_ ? ubqp_ldg16(qsrc + (int64_t)(BROWS * i_) * a.n_pad + (kc) * KC)     \
-                          : uint4{0u, 0u, 0u, 0u};                                            \
+            const bool rin_ = !ROWGUARD || n0 + brow + BROWS * i_ < a.n_pad;                  \
+            br[i_] = (kin_ && rin_) ? ubqp_ldg16(qsrc + (int64_t)(BROWS * i_) * a.n_pad + (kc) * KC) \
+                                    : uint4{0u, 0u, 0u, 0u};                                  \
         }                                                                                     \
         if (TRI && (kc) * KC + KC > n0) {                                                     \
             /* diagonal block: keep bytes with k <= j (j = column, k = byte's K index) */     \
@@ -201,13 +229,13 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     uint64_t awd[FM];
 #define EVAL_READ_A(buf, w)                                                                   \
     _Pragma("unroll") for (int mi = 0; mi < FM; mi++)                                         \
-        awd[mi] = As[buf][(wave * WM + mi * 32 + r32) * APITCH + (w)]
+        awd[mi] = As[buf][(wr * WTM + mi * 32 + r32) * APITCH + (w)]
 #define EVAL_EXPAND_A(dst, half)                                                              \
     _Pragma("unroll") for (int mi = 0; mi < FM; mi++)                                         \
         dst[mi] = expand16((uint32_t)(awd[mi] >> (32 * (half) + 16 * h)) & 0xFFFFu)
 #define EVAL_READ_B(dst, buf, sub)                                                            \
     _Pragma("unroll") for (int ni = 0; ni < FN; ni++)                                         \
-        dst[ni] = *(const v4i *)(&Bs[buf][(ni * 32 + r32) * BPITCH + 32 * (sub) + 16 * h])
+        dst[ni] = *(const v4i *)(&Bs[buf][(wc * WTN + ni * 32 + r32) * BPITCH + 32 * (sub) + 16 * h])
 
     EVAL_LOAD_STAGE(0);
     EVAL_STORE_STAGE(0);
@@ -266,48 +294,76 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
 #undef EVAL_READ_B
 
     // D layout of a 32x32 block: accumulator e of lane l is row 8 (e/4) + 4 (l/32) + e%4,
-    // column l%32.  The 128 columns of the tile are X words n0/64 and n0/64 + 1.
-    const int word0 = n0 >> 6;
+    // column l%32.  The wave's columns [c0, c0 + WTN) are X words c0/64 + k; column
+    // quarter ni (32 columns) is half ni%2 of word ni/2.  n_pad is a multiple of 128,
+    // so a 64-column word lies wholly inside or wholly past n_pad; columns past n_pad
+    // (only in a tile wider than the padding granularity) hold zeros and are
+    // neither counted nor stored.
+    __shared__ uint64_t Xt[KEYS_LDS ? BM * (BN / 64) : 1];
+    if constexpr (KEYS_LDS) {
+        // the staged X words of the tile's columns, for the key epilogue
+#pragma unroll
+        for (int w = 0; w < BN / 64; w++) Xt[tid * (BN / 64) + w] = xt[w];
+        __syncthreads();
+    }
+    constexpr int NWD = WTN / 64;  // X words of the wave's columns
+    const int c0 = n0 + wc * WTN;
+    if (c0 >= a.n_pad) return;
+    bool wok[NWD];
+#pragma unroll
+    for (int k = 0; k < NWD; k++) wok[k] = c0 + 64 * k < a.n_pad;
     if constexpr (EPI == EPI_ROWDOT) {
         const int64_t wgt = plane == 0 ? a.weight0 : 1;
-        // With KC = BN the last K step is the diagonal block [n0, n0 + BN): its staged
-        // X words are this tile's columns and its staged Q block holds q_jj on the
-        // diagonal (kept by the k <= j mask), so both come from LDS.  Nothing is
-        // written to LDS after that step's barrier.
-        constexpr bool LDS_EPI = TRI && KC == BN;
-        const int lastbuf = (nk - 1) & 1;
+        // The triangle's K range ends at n0 + BN, so when the tile's columns span at
+        // most two K steps they are the last two, whose LDS buffers are not written
+        // after their barriers: the staged X words of the columns and the staged Q
+        // block's diagonal (q_jj, kept by the k <= j mask) are read from LDS.
+        constexpr bool LDS_EPI = TRI && ((KC >= BN && KC % BN == 0) || (BN <= 2 * KC && BN % KC == 0));
+        int wbuf[NWD], woff[NWD];  // LDS buffer and word index of each 64-column group
+#pragma unroll
+        for (int k = 0; k < NWD; k++) {
+            const int col = c0 + 64 * k, ks = col / KC;
+            wbuf[k] = ks & 1;
+            woff[k] = (col - ks * KC) >> 6;
+        }
         int32_t dq[FN];  // this plane's q_jj of the lane's columns
 #pragma unroll
         for (int ni = 0; ni < FN; ni++) {
-            const int col = n0 + ni * 32 + r32;
-            if constexpr (LDS_EPI)
-                dq[ni] = Bs[lastbuf][(ni * 32 + r32) * BPITCH + ni * 32 + r32];
-            else
-                dq[ni] = ubqp_ldg1(qp + (int64_t)col * a.n_pad + col);
+            const int col = c0 + ni * 32 + r32;
+            dq[ni] = 0;
+            if (wok[ni >> 1]) {
+                if constexpr (LDS_EPI)
+                    dq[ni] = Bs[wbuf[ni >> 1]][(wc * WTN + ni * 32 + r32) * BPITCH + woff[ni >> 1] * 64 + (ni & 1) * 32 + r32];
+                else
+                    dq[ni] = ubqp_ldg1(qp + (int64_t)col * a.n_pad + col);
+            }
         }
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
             int32_t sv[16];
 #pragma unroll
             for (int e = 0; e < 16; e++) {
-                const int rl = wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int rl = wr * WTM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
                 const int64_t row = m0 + rl;
-                uint64_t xw0 = 0, xw1 = 0;
-                if constexpr (LDS_EPI) {
-                    xw0 = As[lastbuf][rl * APITCH];
-                    xw1 = As[lastbuf][rl * APITCH + 1];
-                } else if (row < Mrows) {
-                    if (word0 < a.W) xw0 = ubqp_ldg8(a.X + row * a.W + word0);
-                    if (word0 + 1 < a.W) xw1 = ubqp_ldg8(a.X + row * a.W + word0 + 1);
+                uint64_t xw[NWD];
+#pragma unroll
+                for (int k = 0; k < NWD; k++) {
+                    xw[k] = 0;
+                    if constexpr (LDS_EPI) {
+                        if (wok[k]) xw[k] = As[wbuf[k]][rl * APITCH + woff[k]];
+                    } else if (row < Mrows && wok[k] && word0_of(c0) + k < a.W) {
+                        xw[k] = ubqp_ldg8(a.X + row * a.W + word0_of(c0) + k);
+                    }
                 }
-                // bit r32 of each 32-column quarter of the tile
-                const uint32_t xq[4] = {(uint32_t)xw0, (uint32_t)(xw0 >> 32), (uint32_t)xw1, (uint32_t)(xw1 >> 32)};
                 int s = 0;
 #pragma unroll
-                for (int ni = 0; ni < FN; ni++) s += ((xq[ni] >> r32) & 1u) ? 2 * acc[mi][ni][e] - dq[ni] : 0;
+                for (int ni = 0; ni < FN; ni++) {
+                    const uint32_t q32 = (uint32_t)(xw[ni >> 1] >> (32 * (ni & 1)));
+                    s += ((q32 >> r32) & 1u) ? 2 * acc[mi][ni][e] - dq[ni] : 0;
+                }
                 sv[e] = s;
             }
-            // |s| <= 4 (2 * 128 n + 128) < 2^24: the 32-lane sums stay inside int32.
+            // |s| <= 8 (2 * 128 n + 128) < 2^25: the 32-lane sums stay inside int32.
             // The 16 rows are reduced in lockstep so that the DPP steps of different
             // rows fill each other's wait states.  Every lane of a quad permutation or
             // a row rotation has a source lane, so bound_ctrl changes nothing but lets
@@ -325,7 +381,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
             if (r32 == 0) {
 #pragma unroll
                 for (int e = 0; e < 16; e++) {
-                    const int64_t row = m0 + wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                    const int64_t row = m0 + wr * WTM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
                     if (row < Mrows && sv[e] != 0) ubqp_atomic_add_i64(&a.f[row], wgt * (int64_t)sv[e]);
                 }
             }
@@ -336,49 +392,45 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
         for (int mi = 0; mi < FM; mi++) {
 #pragma unroll
             for (int e = 0; e < 16; e++) {
-                const int64_t row = m0 + wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int64_t row = m0 + wr * WTM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
                 if (row < Mrows) {
 #pragma unroll
-                    for (int ni = 0; ni < FN; ni++) Yp[row * a.n_pad + n0 + ni * 32 + r32] = acc[mi][ni][e];
+                    for (int ni = 0; ni < FN; ni++)
+                        if (wok[ni >> 1]) Yp[row * a.n_pad + c0 + ni * 32 + r32] = acc[mi][ni][e];
                 }
             }
         }
     } else {
         // Ascent keys of the single-plane problem: with y = (x Q)_j and s = 1 - 2 x_j,
         // Delta_j = q_jj + 2 s y_j, key_j = Delta_j * 256 + 2 (127 - j mod PL) + x_j.
-        __shared__ uint64_t Xt[KEYS_LDS ? BM * (KC / 64) : 1];
         // the key's tie-break part 2 (127 - local index in the ascent lane) per column
         int32_t tb[FN];
 #pragma unroll
-        for (int ni = 0; ni < FN; ni++) tb[ni] = 2 * (127 - (n0 + ni * 32 + r32) % a.keys_pl);
-        if constexpr (KEYS_LDS) {
-#pragma unroll
-            for (int w = 0; w < KC / 64; w++) Xt[tid * (KC / 64) + w] = xt[w];
-            __syncthreads();
-        }
+        for (int ni = 0; ni < FN; ni++) tb[ni] = 2 * (127 - (c0 + ni * 32 + r32) % a.keys_pl);
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
 #pragma unroll
             for (int e = 0; e < 16; e++) {
-                const int rl = wave * WM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int rl = wr * WTM + mi * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
                 const int64_t row = m0 + rl;
                 if (row < Mrows) {
-                    uint64_t xw0 = 0, xw1 = 0;
-                    if constexpr (KEYS_LDS) {
-                        xw0 = Xt[rl * 2];
-                        xw1 = Xt[rl * 2 + 1];
-                    } else {
-                        const int64_t xr = a.rows[row];
-                        const bool ok = xr >= 0 && xr < a.x_rows;
-                        xw0 = (ok && word0 < a.W) ? a.X[xr * a.W + word0] : 0ull;
-                        xw1 = (ok && word0 + 1 < a.W) ? a.X[xr * a.W + word0 + 1] : 0ull;
+                    uint64_t xw[NWD];
+#pragma unroll
+                    for (int k = 0; k < NWD; k++) {
+                        if constexpr (KEYS_LDS) {
+                            xw[k] = Xt[rl * (BN / 64) + wc * NWD + k];
+                        } else {
+                            const int64_t xr = a.rows[row];
+                            const bool ok = xr >= 0 && xr < a.x_rows && word0_of(c0) + k < a.W;
+                            xw[k] = ok ? a.X[xr * a.W + word0_of(c0) + k] : 0ull;
+                        }
                     }
-                    const uint32_t xq[4] = {(uint32_t)xw0, (uint32_t)(xw0 >> 32), (uint32_t)xw1,
-                                            (uint32_t)(xw1 >> 32)};
 #pragma unroll
                     for (int ni = 0; ni < FN; ni++) {
-                        const int col = n0 + ni * 32 + r32;
-                        const int32_t xj = (int32_t)((xq[ni] >> r32) & 1u);
+                        if (!wok[ni >> 1]) continue;
+                        const int col = c0 + ni * 32 + r32;
+                        const uint32_t q32 = (uint32_t)(xw[ni >> 1] >> (32 * (ni & 1)));
+                        const int32_t xj = (int32_t)((q32 >> r32) & 1u);
                         const int32_t y2 = 2 * acc[mi][ni][e];
                         const int32_t delta = dg[ni] + (xj ? -y2 : y2);
                         a.Y[row * a.n_pad + col] = delta * 256 + tb[ni] + xj;
@@ -389,21 +441,26 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     }
 }
 
-// KC = 64 and 128 fit two workgroups per CU (LDS 28 / 48 KB); KC = 256 (90 KB) one.
-template <int EPI, int KC>
-__global__ __launch_bounds__(THR, KC <= 128 ? 2 : 1) void eval_kernel(EvalArgs a, int64_t total)
+// Narrow tiles (BN = 128) with KC = 64 and 128 fit two workgroups per CU (LDS 28 /
+// 48 KB); KC = 256 (90 KB) one.  Wide tiles (BN = 256) hold 256 accumulators per
+// lane: one workgroup per CU.
+template <int KC, int BN> constexpr int eval_min_blocks() { return (BN == 128 && KC <= 128) ? 2 : 1; }
+
+template <int EPI, int KC, int BN, int WR>
+__global__ __launch_bounds__(THR, (eval_min_blocks<KC, BN>())) void eval_kernel(EvalArgs a, int64_t total)
 {
-    eval_body<EPI, KC>(a, xcd_tile(blockIdx.x, total));
+    eval_body<EPI, KC, BN, WR>(a, xcd_tile(blockIdx.x, total));
 }
 
-template <int EPI, int KC>
-__global__ __launch_bounds__(THR, KC <= 128 ? 2 : 1) void eval_batched(const EvalArgs *args, const int64_t *prefix,
-                                                                      int count, int64_t total)
+template <int EPI, int KC, int BN, int WR>
+__global__ __launch_bounds__(THR, (eval_min_blocks<KC, BN>())) void eval_batched(const EvalArgs *args,
+                                                                              const int64_t *prefix, int count,
+                                                                              int64_t total)
 {
     const int64_t t = xcd_tile(blockIdx.x, total);
     const int i = ubqp_find_inst(prefix, count, t);
     const EvalArgs a = args[i];  // a local copy: fields stay in registers across stores
-    eval_body<EPI, KC>(a, t - prefix[i]);
+    eval_body<EPI, KC, BN, WR>(a, t - prefix[i]);
 }
 
 // f[c] = bias * popcount(X_c)^2 (the constant part of the split planes) or 0.
@@ -429,10 +486,14 @@ __global__ __launch_bounds__(256) void eval_init_batched(const EvalArgs *args, c
     eval_init_body(a, blockIdx.x - prefix[i]);
 }
 
-// K depth of the Delta-initialisation contractions (Y rows and keys).
+// K depth and tile geometry of the Delta-initialisation contractions (Y rows and keys).
 #ifndef EVAL_KC
 #define EVAL_KC 128
 #endif
+#ifndef YROWS_BN
+#define YROWS_BN 128
+#endif
+#define YROWS_WR (YROWS_BN == 128 ? 4 : 2)
 
 }  // namespace
 
@@ -451,7 +512,7 @@ EvalArgs ubqp_eval_args(const ubqp_problem *p, const uint64_t *X, int64_t M, int
     a.weight0 = p->weight0;
     a.bias = p->bias;
     a.m_tiles = (int32_t)((M + BM - 1) / BM);
-    a.n_tiles = p->n_pad / BN;
+    a.n_tiles = p->n_pad / UBQP_NPAD_ALIGN;  // column tiles of 128; ubqp_eval_set_variant sets a variant's
     return a;
 }
 
@@ -466,6 +527,7 @@ EvalArgs ubqp_yrows_args(const ubqp_problem *p, const uint64_t *X, int64_t x_row
     a.Y = Y;
     a.diag = p->diag;
     a.keys_pl = p->ncol_a / 64;
+    a.n_tiles = (p->n_pad + YROWS_BN - 1) / YROWS_BN;
     return a;
 }
 
@@ -476,18 +538,41 @@ int64_t ubqp_yrows_tiles(const EvalArgs &a)
 }
 int64_t ubqp_eval_init_blocks(const EvalArgs &a) { return (a.M + 255) / 256; }
 
+// Variants of the row-dot contraction: tiles of 256 x 128 (waves of 64 x 128)
+// staging K 64, 128 or 256 deep; even variants order tiles n-tile-major, odd ones
+// m-tile-major.  (Tiles of 256 x 256 columns with waves of 64 x 256 or 128 x 128,
+// one workgroup per CU, compute the same integers but were measured slower at
+// every n from 1024 to 8192, 0.56 against 0.49 ms at n = 7000, M = 16384: with one
+// wave per SIMD the staging and the per-K-step barrier are no longer hidden.)
 int ubqp_eval_variant_kc(int variant) { return variant / 2 == 0 ? 64 : variant / 2 == 1 ? 128 : 256; }
+int ubqp_eval_variant_bn(int variant)
+{
+    (void)variant;
+    return 128;
+}
+
+void ubqp_eval_set_variant(EvalArgs &a, int variant)
+{
+    a.order = variant & 1;
+    const int bn = ubqp_eval_variant_bn(variant);
+    a.n_tiles = (a.n_pad + bn - 1) / bn;
+}
+
+#define EVAL_VARIANT_SWITCH(LAUNCH)                 \
+    switch (variant) {                              \
+    case 0: case 1: LAUNCH(64, 128, 4); break;      \
+    case 2: case 3: LAUNCH(128, 128, 4); break;     \
+    default: LAUNCH(256, 128, 4); break;            \
+    }
 
 hipError_t ubqp_launch_eval_v(hipStream_t st, EvalArgs a, int variant)
 {
-    a.order = variant & 1;
+    ubqp_eval_set_variant(a, variant);
     hipLaunchKernelGGL(eval_init, dim3((unsigned)ubqp_eval_init_blocks(a)), dim3(256), 0, st, a);
     const int64_t T = ubqp_eval_tiles(a);
-    switch (ubqp_eval_variant_kc(variant)) {
-    case 64: hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, 64>), dim3((unsigned)T), dim3(THR), 0, st, a, T); break;
-    case 128: hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, 128>), dim3((unsigned)T), dim3(THR), 0, st, a, T); break;
-    default: hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, 256>), dim3((unsigned)T), dim3(THR), 0, st, a, T); break;
-    }
+#define L(KC, BN, WR) hipLaunchKernelGGL((eval_kernel<EPI_ROWDOT, KC, BN, WR>), dim3((unsigned)T), dim3(THR), 0, st, a, T)
+    EVAL_VARIANT_SWITCH(L)
+#undef L
     return hipGetLastError();
 }
 
@@ -496,11 +581,9 @@ hipError_t ubqp_launch_eval_rowdot_batch(hipStream_t st, int variant, const Eval
 {
     if (tiles <= 0) return hipSuccess;
     const dim3 g((unsigned)tiles), b(THR);
-    switch (ubqp_eval_variant_kc(variant)) {
-    case 64: hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, 64>), g, b, 0, st, args, prefix, count, tiles); break;
-    case 128: hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, 128>), g, b, 0, st, args, prefix, count, tiles); break;
-    default: hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, 256>), g, b, 0, st, args, prefix, count, tiles); break;
-    }
+#define L(KC, BN, WR) hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, KC, BN, WR>), g, b, 0, st, args, prefix, count, tiles)
+    EVAL_VARIANT_SWITCH(L)
+#undef L
     return hipGetLastError();
 }
 
@@ -508,9 +591,9 @@ hipError_t ubqp_launch_yrows(hipStream_t st, const EvalArgs &a)
 {
     const int64_t T = ubqp_yrows_tiles(a);
     if (a.planes == 1)
-        hipLaunchKernelGGL((eval_kernel<EPI_KEYS, EVAL_KC>), dim3((unsigned)T), dim3(THR), 0, st, a, T);
+        hipLaunchKernelGGL((eval_kernel<EPI_KEYS, EVAL_KC, YROWS_BN, YROWS_WR>), dim3((unsigned)T), dim3(THR), 0, st, a, T);
     else
-        hipLaunchKernelGGL((eval_kernel<EPI_Y, EVAL_KC>), dim3((unsigned)T), dim3(THR), 0, st, a, T);
+        hipLaunchKernelGGL((eval_kernel<EPI_Y, EVAL_KC, YROWS_BN, YROWS_WR>), dim3((unsigned)T), dim3(THR), 0, st, a, T);
     return hipGetLastError();
 }
 
@@ -528,16 +611,16 @@ hipError_t ubqp_launch_eval_batch(hipStream_t st, int epilogue, const EvalArgs *
     if (tiles <= 0) return hipSuccess;
     switch (epilogue) {
     case EPI_ROWDOT:
-        hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, EVAL_KC>), dim3((unsigned)tiles), dim3(THR), 0, st, args, prefix,
-                           count, tiles);
+        hipLaunchKernelGGL((eval_batched<EPI_ROWDOT, EVAL_KC, 128, 4>), dim3((unsigned)tiles), dim3(THR), 0, st, args,
+                           prefix, count, tiles);
         break;
     case EPI_Y:
-        hipLaunchKernelGGL((eval_batched<EPI_Y, EVAL_KC>), dim3((unsigned)tiles), dim3(THR), 0, st, args, prefix,
-                           count, tiles);
+        hipLaunchKernelGGL((eval_batched<EPI_Y, EVAL_KC, YROWS_BN, YROWS_WR>), dim3((unsigned)tiles), dim3(THR), 0, st,
+                           args, prefix, count, tiles);
         break;
     default:
-        hipLaunchKernelGGL((eval_batched<EPI_KEYS, EVAL_KC>), dim3((unsigned)tiles), dim3(THR), 0, st, args, prefix,
-                           count, tiles);
+        hipLaunchKernelGGL((eval_batched<EPI_KEYS, EVAL_KC, YROWS_BN, YROWS_WR>), dim3((unsigned)tiles), dim3(THR), 0,
+                           st, args, prefix, count, tiles);
         break;
     }
     return hipGetLastError();
@@ -546,13 +629,14 @@ hipError_t ubqp_launch_eval_batch(hipStream_t st, int epilogue, const EvalArgs *
 extern "C" int ubqp_eval_ops(const ubqp_problem *p, int64_t M, double *executed, double *dense)
 {
     if (!p || M < 1 || M > UBQP_MAX_M) return UBQP_EINVAL;
-    const int KC = ubqp_eval_variant_kc(ubqp_eval_variant_for(p, M));
+    const int v = ubqp_eval_variant_for(p, M);
+    const int KC = ubqp_eval_variant_kc(v), BN = ubqp_eval_variant_bn(v);
     const int64_t rows = (M + BM - 1) / BM * BM;  // whole row tiles run their matrix ops
     const int nk_full = (p->n_pad + KC - 1) / KC;
     double macs = 0.0;
-    for (int nt = 0; nt < p->n_pad / BN; nt++) {
+    for (int nt = 0; nt * BN < p->n_pad; nt++) {
         const int nk = min(nk_full, (nt * BN + BN + KC - 1) / KC);  // lower triangle: K over [0, n0 + BN)
-        macs += (double)BN * nk * KC;
+        macs += (double)BN * nk * KC;  // every wave runs the K loop, columns past n_pad included
     }
     if (executed) *executed = 2.0 * macs * (double)rows * p->planes;
     if (dense) *dense = 2.0 * (double)p->n * p->n * (double)M * p->planes;

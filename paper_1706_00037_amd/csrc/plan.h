@@ -71,6 +71,8 @@ struct Chunk {
     int lane;  // side stream of its (planes, nb) group: chunks of one group stay in order
     Table<EvalArgs> yr;
     Table<AscArgs> asc;
+    Table<AscArgs> team;  // the same ascents' team launch (few passers), empty when the group never uses teams
+    int n_pad_max = 0;
 };
 
 // Side streams on which the (planes, NB) groups of the Delta initialisation and

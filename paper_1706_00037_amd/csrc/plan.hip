@@ -68,7 +68,7 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
         EvalArgs ea = ubqp_eval_args(p, X, pr.M, f);
         einit.add(ea, ubqp_eval_init_blocks(ea));
         const int variant = ubqp_eval_variant_for(p, pr.M);
-        ea.order = variant & 1;
+        ubqp_eval_set_variant(ea, variant);
         size_t gi = 0;
         while (gi < ev.size() && ev[gi].variant != variant) gi++;
         if (gi == ev.size()) ev.push_back(EvalGroup{variant, {}});
@@ -111,6 +111,8 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
             ch.nb = nb;
             ch.yr.add(yr, ubqp_yrows_tiles(yr));
             ch.asc.add(as, ubqp_ascent_waves(as));
+            if (ubqp_ascent_team_blocks(as) > 0) ch.team.add(as, ubqp_ascent_team_blocks(as));
+            ch.n_pad_max = std::max(ch.n_pad_max, (int)p->n_pad);
         }
         for (auto &kv : groups) {
             // the same (planes, nb) group keeps its side stream across chunk offsets
@@ -139,6 +141,7 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
     for (Chunk &ch : chunks) {
         ch.yr.stage(host);
         ch.asc.stage(host);
+        ch.team.stage(host);
     }
 }
 
@@ -156,6 +159,7 @@ void GenTables::bind(char *dev)
     for (Chunk &ch : chunks) {
         ch.yr.bind(dev);
         ch.asc.bind(dev);
+        ch.team.bind(dev);
     }
 }
 
@@ -223,6 +227,9 @@ hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t 
         Q(ubqp_launch_eval_batch(cs, ch.planes == 1 ? UBQP_EPI_KEYS : UBQP_EPI_Y, ch.yr.d_args, ch.yr.d_pre,
                                  ch.yr.count(), ch.yr.total()));
         if (ae) Q(hipEventRecord(ae[2 * c], cs));
+        if (ch.team.count() > 0)
+            Q(ubqp_launch_ascent_team_batch(cs, ch.n_pad_max, ch.team.d_args, ch.team.d_pre, ch.team.count(),
+                                            ch.team.total()));
         Q(ubqp_launch_ascent_batch(cs, ch.planes, ch.nb, ch.asc.d_args, ch.asc.d_pre, ch.asc.count(),
                                    ch.asc.total()));
         if (ae) Q(hipEventRecord(ae[2 * c + 1], cs));

@@ -2,8 +2,8 @@
 //
 // The contraction Y = X Q has six variants (eval_mfma.hip): K staged 64, 128 or
 // 256 deep per LDS step (two, two or one workgroups per CU) times two tile
-// orders (n-tile-major: neighbouring workgroups share a Q column block in L2;
-// m-tile-major: they share an X row block).  Which is fastest depends on n_pad,
+// orders (n-tile-major: neighbouring workgroups share a Q column
+// block in L2; m-tile-major: they share an X row block).  Which is fastest depends on n_pad,
 // the number of candidates and the number of planes, so the tuner times every
 // variant once per key (planes, n_pad, M rounded up to a power of two) on the
 // problem itself and keeps the fastest for the process.  All variants compute

@@ -11,6 +11,13 @@
 // Tile geometry of the int8 matrix-core contraction Y = X Q (eval_mfma.hip).
 #define UBQP_NPAD_ALIGN 128
 
+// Team ascent (one plane): a launch with at most UBQP_TEAM_MAX_P passers ascends
+// each with UBQP_TEAM waves when the one-wave lane range has at least
+// UBQP_TEAM_MIN_NB blocks of 16 columns (n_pad > 3072).
+#define UBQP_TEAM 4
+#define UBQP_TEAM_MAX_P 512
+#define UBQP_TEAM_MIN_NB 4
+
 // The step-level ubqp_ascent works through passers in chunks of at most this many.
 #define UBQP_ASCENT_CHUNK 4096
 // A multi-start instance's Delta workspace holds at most this many bytes: its
@@ -221,6 +228,7 @@ struct AscArgs {             // steepest 1-flip ascent
     int32_t *flips;
     int32_t max_flips, safety_cap;
     int32_t *err;
+    int64_t team_max;        // launches with at most this many passers ascend them in teams (0: never)
 };
 
 struct RelArgs {             // greedy path relinking, one wave per path
@@ -287,11 +295,15 @@ hipError_t ubqp_launch_eval_init_batch(hipStream_t st, const EvalArgs *args, con
 hipError_t ubqp_launch_eval_batch(hipStream_t st, int epilogue, const EvalArgs *args, const int64_t *prefix,
                                   int count, int64_t tiles);
 
-// Variants of the row-dot contraction (the autotuner's choices): variant v stages
-// K ubqp_eval_variant_kc(v) = 64, 128 or 256 deep (v / 2 = 0, 1, 2) and orders the
-// tiles n-tile-major (v even) or m-tile-major (v odd).
+// Variants of the row-dot contraction (the autotuner's choices): variant v uses
+// column tiles ubqp_eval_variant_bn(v) wide, stages K ubqp_eval_variant_kc(v) deep
+// and orders the tiles n-tile-major (v even) or m-tile-major (v odd).
 #define UBQP_EVAL_DEFAULT_VARIANT 2
 int ubqp_eval_variant_kc(int variant);
+// Column-tile width of a variant (128 for every variant in use).
+int ubqp_eval_variant_bn(int variant);
+// Set a's tile order and column-tile count for a variant (before ubqp_eval_tiles).
+void ubqp_eval_set_variant(EvalArgs &a, int variant);
 hipError_t ubqp_launch_eval_v(hipStream_t st, EvalArgs a, int variant);  // eval_init + contraction
 // The contraction alone, batched; every args[i].order must equal variant & 1.
 hipError_t ubqp_launch_eval_rowdot_batch(hipStream_t st, int variant, const EvalArgs *args, const int64_t *prefix,
@@ -321,6 +333,12 @@ AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, con
                          int32_t *err_flag);
 int ubqp_ascent_nb(const AscArgs &a);
 int64_t ubqp_ascent_waves(const AscArgs &a);
+// Workgroups of the team launch (0 when the launch never uses teams).
+int64_t ubqp_ascent_team_blocks(const AscArgs &a);
+// Team launch of a batched ascent group (one plane); n_pad_max: the largest n_pad
+// of the group (sets the lane range).
+hipError_t ubqp_launch_ascent_team_batch(hipStream_t st, int n_pad_max, const AscArgs *args, const int64_t *prefix,
+                                         int count, int64_t blocks);
 hipError_t ubqp_launch_ascent(hipStream_t st, const AscArgs &a);
 RelArgs ubqp_relink_args(const ubqp_problem *p, const uint64_t *elite, int64_t E, const int32_t *pairs, int64_t P,
                          uint64_t *X, const int32_t *Y, const int64_t *f0, int64_t *f_mid, int64_t *f_out,

@@ -223,6 +223,30 @@ def test_ascent_matches_oracle(ctx, n, M, k, d, lo, hi, mf):
     assert (got_fl[others] == -1).all()
 
 
+@pytest.mark.parametrize("n,P,lo,hi", [(4100, 512, -100, 100),    # a team of four waves per passer
+                                       (4100, 513, -100, 100),    # one wave per passer
+                                       (3073, 40, -3, 3),         # the smallest n_pad with teams, many ties
+                                       (8192, 64, -128, 127)])    # the widest team lanes
+def test_ascent_team_threshold(ctx, n, P, lo, hi):
+    """Launches of at most 512 passers (n_pad > 3072, one plane) ascend each passer
+    with four waves, larger ones with one wave per passer; both give the oracle's
+    rows, values and flip counts, on either side of the threshold."""
+    M = P + 7
+    Q = make_instance(n, 0.2, lo, hi, 8000 + n + P)
+    X = random_candidates(M, n, 8100 + P)
+    f = oracle.eval_many(Q, X, threads=8)
+    idx = np.arange(3, 3 + P, dtype=np.int32)
+    prob = ctx.problem(Q)
+    Xd, fd = dev(X), dev(f)
+    fl = torch.full((M,), -1, dtype=torch.int32, device="cuda")
+    ctx.ascent(prob, Xd, dev(idx), dev(np.array([P], np.int64)), fd, fl)
+    ctx.sync()
+    Xo, fo, flo = oracle.ascent_many(Q, X, idx, f, threads=8)
+    assert np.array_equal(host_u64(Xd), Xo)
+    assert np.array_equal(fd.cpu().numpy(), fo)
+    assert np.array_equal(fl.cpu().numpy()[idx], flo[idx])
+
+
 def test_ascent_device_count_below_capacity(ctx):
     """Only the first *n_idx_d listed rows are ascended."""
     n, M = 300, 40

@@ -44,6 +44,7 @@ CASES = [
     (1, 1.0, -100, 100, 9, 5, 0, (1, 2), 0),
     (90, 0.5, -100, 100, 200, 30, 45, (1, 1), 0),                  # every passer improves
     (1100, 0.2, -100, 100, 300, 200, 0, (1, 2), 0),
+    (4000, 0.3, -100, 100, 300, 100, 0, (1, 2), 0),               # windows ascended in teams of waves
 ]
 
 

@@ -25,7 +25,10 @@ def ctx(ub):
 
 
 @pytest.mark.parametrize("n,M,lo,hi", [(1, 3, -100, 100), (129, 257, -100, 100), (700, 1000, -128, 127),
-                                       (333, 513, -32768, 32767), (2500, 300, -100, 100)])
+                                       (333, 513, -32768, 32767), (2500, 300, -100, 100),
+                                       (7000, 600, -100, 100),        # n_pad 7040: the last wide tile half padding
+                                       (3000, 520, -128, 127),
+                                       (8192, 257, -32768, 32767)])   # the largest n, two planes
 def test_every_variant_matches_oracle(ctx, ub, n, M, lo, hi):
     Q = make_instance(n, 0.4, lo, hi, 300 + n)
     X = random_candidates(M, n, 400 + n)
