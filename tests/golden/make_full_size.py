@@ -16,6 +16,10 @@ the GPU library.  Each case is one JSON file under ``tests/golden/full_size/``:
   serve_first64_G10        the first 64 requests of the serving workload
                            (n ~ U{500..7000}, density ~ U[0.05, 1]), G = 10; the
                            file is rewritten after every request, cheapest first
+  serve_small_G10          every other request with n <= 1500 among the 2100 of
+                           the serving bench's trace (100 warm-up + 2000 timed)
+  ms_n8192_M70000_multichunk  one generation at n = 8192, density 0.05, M = 70000,
+                           lambda = 0: more passers than one Delta workspace holds
 
 A multi-start case records, per generation, the screen statistics {Sum, Max,
 passers, flips, incumbent} and the SHA-256 of every candidate's objective before
@@ -47,6 +51,8 @@ from paper_1706_00037_amd.inputs import (BATCH_PARAMS, BATCH_SUBSET, SERVE_PARAM
 OUT = os.path.join(HERE, "full_size")
 EVAL_CAND_SEED = 31
 SERVE_COUNT = 64
+SERVE_TRACE = 2100      # requests of the serving bench's trace
+SERVE_SMALL_N = 1500
 
 
 def digest(a: np.ndarray) -> str:
@@ -109,14 +115,16 @@ def case_batch(threads: int):
     write("batch_int16_G10", dict(instances=inst))
 
 
-def case_serve(threads: int):
-    reqs = serving_requests(SERVE_COUNT)
-    path = os.path.join(OUT, "serve_first64_G10.json")
+def serve_requests(name: str, count: int, wanted, threads: int):
+    """Oracle results of the requests `wanted` (indices into the first `count` of the
+    serving stream), cheapest first; the file is rewritten after each request."""
+    reqs = serving_requests(count)
+    path = os.path.join(OUT, name + ".json")
     done = {}
     if os.path.exists(path):
         with open(path) as fh:
             done = {int(k): v for k, v in json.load(fh)["requests"].items()}
-    for r in sorted(range(SERVE_COUNT), key=lambda r: reqs[r]["n"]):
+    for r in sorted(wanted, key=lambda r: reqs[r]["n"]):
         if r in done:
             continue
         q = reqs[r]
@@ -125,9 +133,27 @@ def case_serve(threads: int):
         rec = multistart_record(Q, dict(SERVE_PARAMS, run_seed=q["run_seed"]), threads, dump=False)
         rec.update(q)
         done[r] = rec
-        write("serve_first64_G10", dict(count=SERVE_COUNT, requests={str(k): done[k] for k in sorted(done)}))
-        print(f"  request {r} (n={q['n']}) done in {time.time() - t:.0f} s; {len(done)} of {SERVE_COUNT}",
+        write(name, dict(count=count, requests={str(k): done[k] for k in sorted(done)}))
+        print(f"  request {r} (n={q['n']}) done in {time.time() - t:.0f} s; {len(done)} of {len(wanted)}",
               flush=True)
+
+
+def case_serve(threads: int):
+    serve_requests("serve_first64_G10", SERVE_COUNT, range(SERVE_COUNT), threads)
+
+
+def case_serve_small(threads: int):
+    reqs = serving_requests(SERVE_TRACE)
+    wanted = [r for r in range(SERVE_COUNT, SERVE_TRACE) if reqs[r]["n"] <= SERVE_SMALL_N]
+    serve_requests("serve_small_G10", SERVE_TRACE, wanted, threads)
+
+
+def case_multichunk(threads: int):
+    Q = make_instance(8192, 0.05, -100, 100, 818)
+    params = dict(M=70000, H=10, lam_num=0, lam_den=1, G=1, run_seed=5)
+    rec = multistart_record(Q, params, threads)
+    rec.update(n=8192, density=0.05, inst_seed=818)
+    write("ms_n8192_M70000_multichunk", rec)
 
 
 CASES = {
@@ -138,12 +164,15 @@ CASES = {
     "ms7000_4_5": lambda th: case_multistart("n7000_d0.50_M16384", 3, (4, 5), "ms_n7000_M16384_lam4_5_G3", th),
     "batch": case_batch,
     "serve": case_serve,
+    "serve_small": case_serve_small,
+    "multichunk": case_multichunk,
 }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cases", nargs="*", default=list(CASES))
+    # the serving subsets resume from what their files already hold
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     a = ap.parse_args()
     for name in a.cases:

@@ -96,3 +96,29 @@ def test_bench_refuses_more_than_one_gpu():
 def test_flip_limit_rejects_null_problem_without_a_device():
     L = ubqp.load()
     assert L.ubqp_problem_set_flip_limit(None, 5) == ubqp.UBQP_EINVAL
+
+
+def test_bench_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
+    """bench.py reports a kernel's counter traffic only while the kernel's source
+    still has the SHA-256 recorded with the counters."""
+    import hashlib
+    import json
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src = tmp_path / "k.hip"
+    src.write_text("kernel v1\n")
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    table = {"k<1>": {"source": "k.hip", "source_sha256": sha, "gb": 1.5},
+             "k<2>": {"source": "k.hip", "source_sha256": "0" * 64, "gb": 2.5},
+             "k<3>": {"source": "missing.hip", "source_sha256": sha, "gb": 3.5}}
+    md = tmp_path / "counters.md"
+    md.write_text("# counters\n\n```json\n" + json.dumps(table) + "\n```\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(md))
+    monkeypatch.setattr(bench, "CSRC", str(tmp_path))
+    t = bench.load_traffic()
+    assert t["k<1>"]["gb"] == 1.5 and t["k<2>"] is None and t["k<3>"] is None
+    src.write_text("kernel v2\n")                     # the kernel changed since the counters
+    assert bench.load_traffic()["k<1>"] is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.md"))
+    assert bench.load_traffic() == {}

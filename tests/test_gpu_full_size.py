@@ -13,7 +13,10 @@ oracle wrote (tests/golden/make_full_size.py; nothing in them comes from the GPU
 * four int16 instances shaped like the batched workload through one batch
   (autotuned tiles), ten generations: statistics and incumbents;
 * the first 64 requests of the serving workload through the request server, all
-  submitted at once so that they share generations: statistics and incumbents.
+  submitted at once so that they share generations, and every other request with
+  n <= 1500 of the serving bench's 2100-request trace: statistics and incumbents;
+* one generation at n = 8192, M = 70000, lambda = 0: more passers than one Delta
+  workspace holds, ascended in two chunks.
 Launch configuration: the one bench.py times (graph-replayed generations, the
 default evaluation variant, or the autotuned one where the bench tunes).
 """
@@ -132,10 +135,19 @@ def test_batched_int16_instances(ctx):
         _same_as_golden(r, gk, k)
 
 
+@pytest.mark.timeout(600)
+def test_multistart_n8192_multichunk(ctx):
+    g = golden("ms_n8192_M70000_multichunk")
+    Q = make_instance(g["n"], g["density"], -100, 100, g["inst_seed"])
+    assert g["stats"][0][2] > 32768                 # the second Delta workspace chunk holds passers
+    _check_run(ctx, Q, g)
+
+
 @pytest.mark.timeout(900)
-def test_serving_first_requests(ctx):
+@pytest.mark.parametrize("name", ["serve_first64_G10", "serve_small_G10"])
+def test_serving_requests(ctx, name):
     from paper_1706_00037_amd import ubqp
-    g = golden("serve_first64_G10")
+    g = golden(name)
     reqs = serving_requests(g["count"])
     want = {int(k): v for k, v in g["requests"].items()}
     srv = ctx.server(pool_bytes=48 << 30, max_active=32)
