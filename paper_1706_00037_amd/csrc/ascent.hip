@@ -656,17 +656,21 @@ __global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_i8_team_batched(const A
 // 2 |q| <= 65534 and a path has fewer than 8192 flips, so they stay inside
 // [-2.14e9, -1.06e9], below every real Delta (|Delta| < 5.4e8) and clear of
 // int32 overflow.  The best intermediate is kept as a copy of the sign bytes.
+// T = UBQP_TEAM walks a path with four waves (the team layout of the ascent: wave
+// w's virtual lanes 64 w + l own consecutive ranges, the waves' best steps combined
+// through LDS once per step); T = 1 with one wave.
 constexpr int32_t RL_GONE = -1600000000;
 
-template <int NB, int PLANES>
-__device__ void relink_path(const RelArgs &a, int64_t p, int lane)
+template <int NB, int PLANES, int T>
+__device__ void relink_path(const RelArgs &a, int64_t p, int wv, int lane, int2 (*slots)[UBQP_TEAM])
 {
     constexpr int PL = 16 * NB;
-    const int col_base = lane * PL;
+    const int vl = wv * 64 + lane;  // virtual lane
+    const int col_base = vl * PL;
     const int64_t ii = a.pairs[2 * p], gi = a.pairs[2 * p + 1];
     uint64_t *xr = a.X + p * a.W;
-    if (ii < 0 || ii >= a.E || gi < 0 || gi >= a.E) {
-        if (lane == 0) {
+    if (ii < 0 || ii >= a.E || gi < 0 || gi >= a.E) {  // the same for every wave of a team
+        if (vl == 0) {
             atomicOr(a.err, 2);
             a.f_mid[p] = INT64_MIN;
             a.f_out[p] = INT64_MIN;
@@ -740,6 +744,7 @@ __device__ void relink_path(const RelArgs &a, int64_t p, int lane)
         for (int r = 0; r < 4; r++) sb[b][r] = ss[b][r];
     int64_t fv = a.f0[p], best = INT64_MIN;
     int32_t bstep = 0;
+    int par = 0;
     __builtin_amdgcn_s_waitcnt(WAIT_VM_LGKM_0);
     for (int s = 1; s < nd; s++) {
         int32_t bm[NB];
@@ -770,20 +775,38 @@ __device__ void relink_path(const RelArgs &a, int64_t p, int lane)
             for (int r = 0; r < 4; r++)
                 if (b == bs && r == (ts >> 2)) sword = ss[b][r];
         const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)sword, lstar);
-        const int32_t xk = ((sk >> (8 * (ts & 3))) & 0xFFu) == 0xFFu;  // x_k before the flip
-        const int K = lstar * PL + 16 * bs + ts;
-        const bool own = lane == lstar;
-        const uint32_t sflip = own ? 0xFEu << (8 * (ts & 3)) : 0u;
+        int32_t xk = ((sk >> (8 * (ts & 3))) & 0xFFu) == 0xFFu;  // x_k before the flip
+        int K = (wv * 64 + lstar) * PL + 16 * bs + ts;
+        int32_t Vs = V;
+        bool own = lane == lstar;
+        if constexpr (T > 1) {
+            // the team's step: the largest Delta of the waves, the lowest wave on ties
+            if (lane == 0) slots[par][wv] = int2{V, K | (xk << 30)};
+            __syncthreads();
+            int2 win = slots[par][0];
+#pragma unroll
+            for (int u = 1; u < T; u++) {
+                const int2 o = slots[par][u];
+                win = o.x > win.x ? o : win;
+            }
+            par ^= 1;
+            Vs = win.x;
+            K = win.y & 0x3FFFFFFF;
+            xk = (win.y >> 30) & 1;
+            own = vl == K / PL;
+        }
+        const int bs_k = (K % PL) >> 4, ts_k = K & 15;
+        const uint32_t sflip = own ? 0xFEu << (8 * (ts_k & 3)) : 0u;
 #pragma unroll
         for (int b = 0; b < NB; b++) {
-            if (b == bs) {
-                const int32_t ko = dl[b][ts];
-                dl[b][ts] = own ? RL_GONE : ko;   // retired from the free set
+            if (b == bs_k) {
+                const int32_t ko = dl[b][ts_k];
+                dl[b][ts_k] = own ? RL_GONE : ko;   // retired from the free set
 #pragma unroll
-                for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts >> 2)) ? sflip : 0u;
+                for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts_k >> 2)) ? sflip : 0u;
             }
         }
-        fv += V;
+        fv += Vs;
         if (fv > best) {
             best = fv;
             bstep = s;
@@ -797,8 +820,10 @@ __device__ void relink_path(const RelArgs &a, int64_t p, int lane)
         if (PLANES == 1) {
             const int8_t *row = (const int8_t *)a.qa + (int64_t)K * a.ncol_a + col_base;
             uint4 w[NB];
+            // a team's virtual lanes can reach past the row's ncol_a columns
 #pragma unroll
-            for (int b = 0; b < NB; b++) w[b] = ubqp_ldg16(row + 16 * b);
+            for (int b = 0; b < NB; b++)
+                w[b] = (T == 1 || col_base + 16 * b < a.ncol_a) ? ubqp_ldg16(row + 16 * b) : uint4{0u, 0u, 0u, 0u};
 #pragma unroll
             for (int b = 0; b < NB; b++) {
                 int32_t d[16];
@@ -815,8 +840,9 @@ __device__ void relink_path(const RelArgs &a, int64_t p, int lane)
             uint4 w[NB][2];
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                w[b][0] = ubqp_ldg16(row + 16 * b);
-                w[b][1] = ubqp_ldg16(row + 16 * b + 8);
+                const bool in = T == 1 || col_base + 16 * b < a.ncol_a;
+                w[b][0] = in ? ubqp_ldg16(row + 16 * b) : uint4{0u, 0u, 0u, 0u};
+                w[b][1] = in ? ubqp_ldg16(row + 16 * b + 8) : uint4{0u, 0u, 0u, 0u};
             }
 #pragma unroll
             for (int b = 0; b < NB; b++) {
@@ -838,21 +864,33 @@ __device__ void relink_path(const RelArgs &a, int64_t p, int lane)
             uint32_t bits = 0;
 #pragma unroll
             for (int t = 0; t < 16; t++) bits |= (((sb[b][t >> 2] >> (8 * (t & 3))) & 0xFFu) == 0xFFu ? 1u : 0u) << t;
-            const int ci = lane * NB + b;
+            const int ci = vl * NB + b;
             if (ci < 4 * a.W) ((uint16_t *)xr)[ci] = (uint16_t)bits;
         }
     }
-    if (lane == 0) {
+    if (vl == 0) {
         a.f_mid[p] = best;
         a.f_out[p] = best;
         a.steps[p] = bstep;
     }
+    // the next path's first step writes slot set 0, which slower waves of the team may
+    // still be reading in this path's last step
+    if constexpr (T > 1) __syncthreads();
 }
 
 template <int NB, int PLANES>
 __global__ __launch_bounds__(64, NB <= 4 ? 2 : 1) void relink_kernel(RelArgs a)
 {
-    for (int64_t p = blockIdx.x; p < a.P; p += gridDim.x) relink_path<NB, PLANES>(a, p, threadIdx.x);
+    for (int64_t p = blockIdx.x; p < a.P; p += gridDim.x) relink_path<NB, PLANES, 1>(a, p, 0, threadIdx.x, nullptr);
+}
+
+// Few paths (at most UBQP_TEAM_MAX_P, n_pad > 3072): four waves per path.
+template <int NBT, int PLANES>
+__global__ __launch_bounds__(64 * UBQP_TEAM) void relink_team_kernel(RelArgs a)
+{
+    __shared__ int2 slots[2][UBQP_TEAM];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t p = blockIdx.x; p < a.P; p += gridDim.x) relink_path<NBT, PLANES, UBQP_TEAM>(a, p, wv, lane, slots);
 }
 
 #define UBQP_NB_SWITCH(nb, LAUNCH) \
@@ -998,6 +1036,18 @@ RelArgs ubqp_relink_args(const ubqp_problem *p, const uint64_t *elite, int64_t E
 hipError_t ubqp_launch_relink(hipStream_t st, const RelArgs &a)
 {
     if (a.P <= 0) return hipSuccess;
+    if (a.P <= UBQP_TEAM_MAX_P && (a.n_pad + 1023) / 1024 >= UBQP_TEAM_MIN_NB) {
+        const unsigned blocks = (unsigned)a.P;
+        const bool two = (a.n_pad + 4095) / 4096 > 1;
+        if (a.planes == 2) {
+            if (two) hipLaunchKernelGGL((relink_team_kernel<2, 2>), dim3(blocks), dim3(64 * UBQP_TEAM), 0, st, a);
+            else hipLaunchKernelGGL((relink_team_kernel<1, 2>), dim3(blocks), dim3(64 * UBQP_TEAM), 0, st, a);
+        } else {
+            if (two) hipLaunchKernelGGL((relink_team_kernel<2, 1>), dim3(blocks), dim3(64 * UBQP_TEAM), 0, st, a);
+            else hipLaunchKernelGGL((relink_team_kernel<1, 1>), dim3(blocks), dim3(64 * UBQP_TEAM), 0, st, a);
+        }
+        return hipGetLastError();
+    }
     const unsigned waves = (unsigned)(a.P < 8192 ? a.P : 8192);
     const int nb = (a.n_pad + 1023) / 1024;
 #define L1(NB) hipLaunchKernelGGL((relink_kernel<NB, 1>), dim3(waves), dim3(64), 0, st, a)

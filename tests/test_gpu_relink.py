@@ -77,6 +77,28 @@ def test_relink_largest_shapes_sampled(ctx, n, lo, hi, d):
     assert (r["f_out"][r["steps"] > 0] >= r["f_mid"][r["steps"] > 0]).all()
 
 
+@pytest.mark.parametrize("P,lo,hi", [(512, -100, 100), (513, -100, 100), (300, -32768, 32767)])
+def test_relink_team_threshold(ctx, P, lo, hi):
+    """At most 512 paths with n_pad > 3072 are walked by teams of four waves, more
+    by one wave each; both give the oracle's steps, values and rows."""
+    n = 3100
+    Q = make_instance(n, 0.2, lo, hi, 8900 + P)
+    elite = _elite(n, 24, 8901)
+    pairs = np.array([(a, b) for a in range(24) for b in range(24) if a != b], np.int32)[:P]
+    prob = ctx.problem(Q)
+    X = torch.empty((P, prob.W), dtype=torch.int64, device="cuda")
+    fm = torch.empty(P, dtype=torch.int64, device="cuda")
+    fo = torch.empty(P, dtype=torch.int64, device="cuda")
+    st = torch.empty(P, dtype=torch.int32, device="cuda")
+    ctx.relink(prob, torch.from_numpy(elite.view(np.int64)).cuda(), torch.from_numpy(pairs).cuda(), X, fm, fo, st)
+    ctx.sync()
+    o = oracle.relink_many(Q, elite, pairs, threads=8)
+    assert np.array_equal(st.cpu().numpy(), o["steps"])
+    assert np.array_equal(fm.cpu().numpy(), o["f_mid"])
+    assert np.array_equal(fo.cpu().numpy(), o["f_out"])
+    assert np.array_equal(X.cpu().numpy().view(np.uint64), o["X"])
+
+
 def test_relink_rejects_bad_arguments(ctx, ub):
     n = 70
     prob = ctx.problem(make_instance(n, 0.5, -100, 100, 1))
