@@ -27,7 +27,8 @@ def dev(a):
     return torch.from_numpy(a.view(np.int64) if a.dtype == np.uint64 else a).cuda()
 
 
-@pytest.mark.parametrize("n,lo,hi", [(500, -100, 100), (700, -32768, 32767)])
+@pytest.mark.parametrize("n,lo,hi", [(500, -100, 100), (700, -32768, 32767),
+                                     (4000, -100, 100)])   # a team of four waves per passer
 def test_step_ascent_reports_the_limit(ctx, n, lo, hi):
     from paper_1706_00037_amd import ubqp
     M = 32

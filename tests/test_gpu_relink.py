@@ -99,10 +99,10 @@ def test_relink_team_threshold(ctx, P, lo, hi):
     assert np.array_equal(X.cpu().numpy().view(np.uint64), o["X"])
 
 
-def test_relink_rejects_bad_arguments(ctx, ub):
-    n = 70
+@pytest.mark.parametrize("n", [70, 3100])                 # one wave per path; a team of four
+def test_relink_rejects_bad_arguments(ctx, ub, n):
     prob = ctx.problem(make_instance(n, 0.5, -100, 100, 1))
-    W = 2
+    W = prob.W
     elite = torch.zeros((3, W), dtype=torch.int64, device="cuda")
     X = torch.zeros((2, W), dtype=torch.int64, device="cuda")
     f = torch.zeros(2, dtype=torch.int64, device="cuda")
