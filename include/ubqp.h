@@ -112,7 +112,10 @@ typedef struct ubqp_batch ubqp_batch;  /* library-owned: several runs advanced t
 UBQP_API int ubqp_create(ubqp_ctx **out, int device, void *stream);
 /* Change the stream later calls launch on. */
 UBQP_API int ubqp_set_stream(ubqp_ctx *ctx, void *stream);
-/* Release the context and its workspace.  Problems created on it must be destroyed first. */
+/* Release the context and its workspace.  Problems, runs, batches and servers
+ * created on it may still be alive: the context is then freed when the last of
+ * them is destroyed (their destroy calls stay valid; no other call may take the
+ * context after this one).  Call it once per context. */
 UBQP_API int ubqp_destroy(ubqp_ctx *ctx);
 /* Message describing the last error on ctx (never NULL; "" if none). */
 UBQP_API const char *ubqp_last_error(const ubqp_ctx *ctx);

@@ -98,6 +98,23 @@ int ubqp_check_params(ubqp_ctx *ctx, const ubqp_problem *p, const ubqp_params *p
     return UBQP_OK;
 }
 
+static void ctx_free(ubqp_ctx *ctx)
+{
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int i = 0; i < ubqp_ctx::WS_COUNT; i++)
+        if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
+    (void)hipFree(ctx->err_flag);
+    delete ctx;
+}
+
+void ubqp_ctx_hold(ubqp_ctx *ctx) { ctx->hold.fetch_add(2); }
+
+void ubqp_ctx_drop(ubqp_ctx *ctx)
+{
+    if (ctx->hold.fetch_sub(2) == 3) ctx_free(ctx);  // the last holder of a released context
+}
+
 extern "C" {
 
 int ubqp_create(ubqp_ctx **out, int device, void *stream)
@@ -134,12 +151,9 @@ int ubqp_set_stream(ubqp_ctx *ctx, void *stream)
 int ubqp_destroy(ubqp_ctx *ctx)
 {
     if (!ctx) return UBQP_EINVAL;
-    (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
-    for (int i = 0; i < ubqp_ctx::WS_COUNT; i++)
-        if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
-    (void)hipFree(ctx->err_flag);
-    delete ctx;
+    const int64_t old = ctx->hold.fetch_or(1);
+    if (old & 1) return UBQP_EINVAL;  // released before
+    if (old == 0) ctx_free(ctx);      // else the last problem, run, batch or server frees it
     return UBQP_OK;
 }
 

@@ -273,8 +273,9 @@ namespace {
 void plan_free(ubqp_plan *pl)
 {
     if (!pl) return;
-    (void)hipSetDevice(pl->ctx->device);
-    (void)hipStreamSynchronize(pl->ctx->stream);
+    ubqp_ctx *ctx = pl->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
@@ -289,6 +290,7 @@ void plan_free(ubqp_plan *pl)
     if (pl->state) (void)hipFree(pl->state);
     if (pl->tables) (void)hipFree(pl->tables);
     delete pl;
+    ubqp_ctx_drop(ctx);
 }
 
 int plan_create(ubqp_ctx *ctx, int count, const ubqp_problem *const *probs, const ubqp_params *params,
@@ -308,6 +310,7 @@ int plan_create(ubqp_ctx *ctx, int count, const ubqp_problem *const *probs, cons
     ubqp_plan *pl = new (std::nothrow) ubqp_plan();
     if (!pl) return ubqp_fail(ctx, UBQP_ENOMEM, "host allocation");
     pl->ctx = ctx;
+    ubqp_ctx_hold(ctx);
     pl->count = count;
     pl->G = params[0].G;
     pl->timing = (params[0].flags & UBQP_TIMING) != 0;

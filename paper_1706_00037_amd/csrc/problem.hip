@@ -231,6 +231,7 @@ int ubqp_problem_create_typed(ubqp_ctx *ctx, int32_t n, const void *q, int32_t e
     ubqp_problem *p = new (std::nothrow) ubqp_problem();
     if (!p) return ubqp_fail(ctx, UBQP_ENOMEM, "host allocation");
     p->ctx = ctx;
+    ubqp_ctx_hold(ctx);
     ubqp_problem_geometry(p, n, (hf.bits & UBQP_CHECK_WIDE) ? 2 : 1);
     hipError_t e = hipMalloc(&p->mem, ubqp_problem_bytes(p));
     if (e == hipSuccess) {
@@ -254,10 +255,12 @@ int ubqp_problem_create(ubqp_ctx *ctx, int32_t n, const int32_t *q_host, ubqp_pr
 int ubqp_problem_destroy(ubqp_problem *p)
 {
     if (!p) return UBQP_EINVAL;
-    (void)hipSetDevice(p->ctx->device);
-    (void)hipStreamSynchronize(p->ctx->stream);
+    ubqp_ctx *ctx = p->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
     if (p->mem) (void)hipFree(p->mem);
     delete p;
+    ubqp_ctx_drop(ctx);
     return UBQP_OK;
 }
 

@@ -541,7 +541,8 @@ void worker_main(ubqp_server *s)
 
 void server_free(ubqp_server *s)
 {
-    (void)hipSetDevice(s->ctx->device);
+    ubqp_ctx *ctx = s->ctx;
+    (void)hipSetDevice(ctx->device);
     if (s->cs) (void)hipStreamSynchronize(s->cs);
     if (s->up) (void)hipStreamSynchronize(s->up);
     s->side.destroy();
@@ -561,6 +562,7 @@ void server_free(ubqp_server *s)
     if (s->up) (void)hipStreamDestroy(s->up);
     if (s->cs) (void)hipStreamDestroy(s->cs);
     delete s;
+    ubqp_ctx_drop(ctx);
 }
 
 }  // namespace
@@ -585,6 +587,7 @@ int ubqp_server_create(ubqp_ctx *ctx, int64_t pool_bytes, int32_t max_active, ub
     ubqp_server *s = new (std::nothrow) ubqp_server();
     if (!s) return ubqp_fail(ctx, UBQP_ENOMEM, "host allocation");
     s->ctx = ctx;
+    ubqp_ctx_hold(ctx);
     s->max_active = max_active;
     for (auto &c : s->cnt) c = 0;
     const size_t pb = ubqp_align256((size_t)pool_bytes);

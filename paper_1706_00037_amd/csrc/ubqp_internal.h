@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 
 #include "../../include/ubqp.h"
@@ -35,7 +36,15 @@ struct ubqp_ctx {
     void *ws[WS_COUNT] = {};
     size_t ws_bytes[WS_COUNT] = {};
     int32_t *err_flag = nullptr;  // device int32: kernel-side checks (bit 0: flip limit, bit 1: index skipped)
+    // Twice the number of live problems, runs, batches and servers created on the
+    // context, plus 1 once ubqp_destroy has been called: the context is freed when
+    // the call has come and the last of them is gone, in whichever order.
+    std::atomic<int64_t> hold{0};
 };
+// A problem, run, batch or server that keeps ctx alive (hold when it takes the
+// context, drop when it is freed; the drop frees a released context).
+void ubqp_ctx_hold(ubqp_ctx *ctx);
+void ubqp_ctx_drop(ubqp_ctx *ctx);
 
 struct ubqp_problem {
     ubqp_ctx *ctx = nullptr;
