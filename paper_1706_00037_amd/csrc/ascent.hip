@@ -286,17 +286,20 @@ __device__ inline void update_deltas8(int32_t &d0, int32_t &d1, int32_t &d2, int
 // and the wave's maximum V; the lowest lane attaining V, then (in that lane) its
 // lowest block and lowest column attaining V -- the lowest global column.  The
 // update is one SDWA multiply (q word x s byte) and one mad by the uniform 2 d.
-template <int NB>
-__device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
+// T = UBQP_TEAM: the team layout of ascend_i8_team (four waves per passer, each
+// flip's best of the waves combined through LDS); T = 1: one wave.
+template <int NB, int T>
+__device__ void ascend_i16(const AscArgs &a, int64_t p, int wv, int lane, int2 (*slots)[UBQP_TEAM])
 {
     constexpr int PL = 16 * NB;
+    const int vl = wv * 64 + lane;  // virtual lane
     const int64_t c = a.idx[a.offset + p];
-    if (c < 0 || c >= a.x_rows) {
-        if (lane == 0) atomicOr(a.err, 2);
+    if (c < 0 || c >= a.x_rows) {  // the same for every wave of a team
+        if (vl == 0) atomicOr(a.err, 2);
         return;
     }
     uint64_t *xr = a.X + c * a.W;
-    const int col_base = lane * PL;
+    const int col_base = vl * PL;
     // popcount(x) for the constant part of the split planes
     int pc = 0;
     for (int w = lane; w < a.W; w += 64) pc += __popcll(xr[w]);
@@ -347,6 +350,7 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
     int32_t flips = 0;
     const int32_t cap = a.max_flips > 0 ? a.max_flips : a.safety_cap;
     int32_t V;
+    int par = 0;
     __builtin_amdgcn_s_waitcnt(WAIT_VM_LGKM_0);
     for (;;) {
         int32_t bm[NB];
@@ -356,7 +360,7 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
 #pragma unroll
         for (int b = 1; b < NB; b++) best = max(best, bm[b]);
         V = wave_max_i32(best);
-        if (V <= 0 || flips >= cap) break;
+        if (T == 1 && (V <= 0 || flips >= cap)) break;
         const int lstar = __ffsll((unsigned long long)__ballot(best == V)) - 1;
         int bsel = NB - 1;
 #pragma unroll
@@ -378,17 +382,35 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
             for (int r = 0; r < 4; r++)
                 if (b == bs && r == (ts >> 2)) sword = ss[b][r];
         const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)sword, lstar);
-        const int32_t xk = ((sk >> (8 * (ts & 3))) & 0xFFu) == 0xFFu;   // x_k before the flip
-        const int K = lstar * PL + 16 * bs + ts;
-        const bool own = lane == lstar;
-        const uint32_t sflip = own ? 0xFEu << (8 * (ts & 3)) : 0u;
+        int32_t xk = ((sk >> (8 * (ts & 3))) & 0xFFu) == 0xFFu;   // x_k before the flip
+        int K = (wv * 64 + lstar) * PL + 16 * bs + ts;
+        bool own = lane == lstar;
+        if constexpr (T > 1) {
+            // the team's flip: the largest Delta of the waves, the lowest wave on ties
+            if (lane == 0) slots[par][wv] = int2{V, K | (xk << 30)};
+            __syncthreads();
+            int2 win = slots[par][0];
+#pragma unroll
+            for (int u = 1; u < T; u++) {
+                const int2 o = slots[par][u];
+                win = o.x > win.x ? o : win;
+            }
+            par ^= 1;
+            V = win.x;
+            if (V <= 0 || flips >= cap) break;
+            K = win.y & 0x3FFFFFFF;
+            xk = (win.y >> 30) & 1;
+            own = vl == K / PL;
+        }
+        const int bs_k = (K % PL) >> 4, ts_k = K & 15;
+        const uint32_t sflip = own ? 0xFEu << (8 * (ts_k & 3)) : 0u;
 #pragma unroll
         for (int b = 0; b < NB; b++) {
-            if (b == bs) {
-                const int32_t ko = dl[b][ts];
-                dl[b][ts] = own ? -V : ko;
+            if (b == bs_k) {
+                const int32_t ko = dl[b][ts_k];
+                dl[b][ts_k] = own ? -V : ko;
 #pragma unroll
-                for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts >> 2)) ? sflip : 0u;
+                for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts_k >> 2)) ? sflip : 0u;
             }
         }
         gain += V;
@@ -397,10 +419,12 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
         const int32_t step = xk ? -2 : 2;
         const int16_t *row = qa + (int64_t)K * a.ncol_a + col_base;
         uint4 w[NB][2];
+        // a team's virtual lanes can reach past the row's ncol_a columns
 #pragma unroll
         for (int b = 0; b < NB; b++) {
-            w[b][0] = ubqp_ldg16(row + 16 * b);
-            w[b][1] = ubqp_ldg16(row + 16 * b + 8);
+            const bool in = T == 1 || col_base + 16 * b < a.ncol_a;
+            w[b][0] = in ? ubqp_ldg16(row + 16 * b) : uint4{0u, 0u, 0u, 0u};
+            w[b][1] = in ? ubqp_ldg16(row + 16 * b + 8) : uint4{0u, 0u, 0u, 0u};
         }
         __builtin_amdgcn_s_setprio(1);  // as in the int8 ascent
 #pragma unroll
@@ -417,20 +441,23 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int lane)
         }
         __builtin_amdgcn_s_setprio(0);
     }
-    if (V > 0 && a.max_flips == 0 && lane == 0) atomicOr(a.err, 1);  // safety cap reached
+    if (V > 0 && a.max_flips == 0 && vl == 0) atomicOr(a.err, 1);  // flip limit reached
 
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         uint32_t bits = 0;
 #pragma unroll
         for (int t = 0; t < 16; t++) bits |= (((ss[b][t >> 2] >> (8 * (t & 3))) & 0xFFu) == 0xFFu ? 1u : 0u) << t;
-        const int ci = lane * NB + b;
+        const int ci = vl * NB + b;
         if (ci < 4 * a.W) ((uint16_t *)xr)[ci] = (uint16_t)bits;
     }
-    if (lane == 0) {
+    if (vl == 0) {
         a.f[c] += gain;
         a.flips[c] = flips;
     }
+    // the next passer's first flip writes slot set 0, which slower waves of the team
+    // may still be reading in this passer's last flip
+    if constexpr (T > 1) __syncthreads();
 }
 
 // One wave per workgroup: a wave whose candidate needs few flips retires at once
@@ -459,7 +486,8 @@ __global__ __launch_bounds__(64, NB <= 4 ? 3 : 2) void ascent_i16_kernel(AscArgs
 {
     int64_t P = *a.nidx_d - a.offset;
     P = P < a.max_idx ? P : a.max_idx;
-    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_i16<NB>(a, p, threadIdx.x);
+    if (P <= a.team_max) return;  // the team kernel of the same launch takes these passers
+    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_i16<NB, 1>(a, p, 0, threadIdx.x, nullptr);
 }
 
 template <int NB>
@@ -470,7 +498,8 @@ __global__ __launch_bounds__(64, NB <= 4 ? 3 : 2) void ascent_i16_batched(const 
     const int64_t w0 = blockIdx.x - prefix[i], nw = prefix[i + 1] - prefix[i];
     int64_t P = *a.nidx_d - a.offset;
     P = P < a.max_idx ? P : a.max_idx;
-    for (int64_t p = w0; p < P; p += nw) ascend_i16<NB>(a, p, threadIdx.x);
+    if (P <= a.team_max) return;  // the team kernel of the same launch takes these passers
+    for (int64_t p = w0; p < P; p += nw) ascend_i16<NB, 1>(a, p, 0, threadIdx.x, nullptr);
 }
 
 template <int NB>
@@ -486,8 +515,8 @@ __global__ __launch_bounds__(64, AscOcc<NB>::waves) void ascent_i8_batched(const
 }
 
 // ---- team ascent: few passers, four waves each ----------------------------------
-// A launch with at most UBQP_TEAM_MAX_P passers leaves most SIMDs idle, and each
-// passer's flip chain (a row read, then the update and argmax of all its columns
+// A launch with at most UBQP_TEAM_MAX_P passers (one per SIMD) leaves most wave
+// slots idle, and each passer's flip chain (a row read, then the update and argmax of all its columns
 // by one wave) is the launch's critical path.  There four waves share a passer:
 // virtual lane v = 64 w + l of wave w owns the columns [v PLT, (v+1) PLT),
 // PLT = 16 NBT, a quarter of the one-wave range, so each wave reads a quarter of
@@ -619,20 +648,27 @@ __device__ void ascend_i8_team(const AscArgs &a, int64_t p, int w, int lane, int
 // Team kernels: one workgroup of UBQP_TEAM waves per passer.  They run only when
 // the launch's passer count is at most UBQP_TEAM_MAX_P (the one-wave kernels take
 // the other launches and return at once here, and the other way round).
-template <int NBT>
-__global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_i8_team_kernel(AscArgs a)
+template <int NBT, int PLANES>
+__device__ inline void ascend_team(const AscArgs &a, int64_t p, int w, int lane, int2 (*slots)[UBQP_TEAM])
+{
+    if constexpr (PLANES == 1) ascend_i8_team<NBT>(a, p, w, lane, slots);
+    else ascend_i16<NBT, UBQP_TEAM>(a, p, w, lane, slots);
+}
+
+template <int NBT, int PLANES>
+__global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_team_kernel(AscArgs a)
 {
     __shared__ int2 slots[2][UBQP_TEAM];
     int64_t P = *a.nidx_d - a.offset;
     P = P < a.max_idx ? P : a.max_idx;
     if (P > a.team_max) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_i8_team<NBT>(a, p, w, lane, slots);
+    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_team<NBT, PLANES>(a, p, w, lane, slots);
 }
 
-template <int NBT>
-__global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_i8_team_batched(const AscArgs *args, const int64_t *prefix,
-                                                                          int count)
+template <int NBT, int PLANES>
+__global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_team_batched(const AscArgs *args, const int64_t *prefix,
+                                                                       int count)
 {
     __shared__ int2 slots[2][UBQP_TEAM];
     const int i = ubqp_find_inst(prefix, count, blockIdx.x);
@@ -642,7 +678,7 @@ __global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_i8_team_batched(const A
     P = P < a.max_idx ? P : a.max_idx;
     if (P > a.team_max) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int64_t p = b0; p < P; p += nb) ascend_i8_team<NBT>(a, p, w, lane, slots);
+    for (int64_t p = b0; p < P; p += nb) ascend_team<NBT, PLANES>(a, p, w, lane, slots);
 }
 
 // ---- greedy path relinking -------------------------------------------------
@@ -884,7 +920,7 @@ __global__ __launch_bounds__(64, NB <= 4 ? 2 : 1) void relink_kernel(RelArgs a)
     for (int64_t p = blockIdx.x; p < a.P; p += gridDim.x) relink_path<NB, PLANES, 1>(a, p, 0, threadIdx.x, nullptr);
 }
 
-// Few paths (at most UBQP_TEAM_MAX_P, n_pad > 3072): four waves per path.
+// Few paths (at most UBQP_RELINK_TEAM_MAX_P, n_pad > 3072): four waves per path.
 template <int NBT, int PLANES>
 __global__ __launch_bounds__(64 * UBQP_TEAM) void relink_team_kernel(RelArgs a)
 {
@@ -933,10 +969,15 @@ AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, con
     a.max_flips = max_flips;
     a.safety_cap = ubqp_problem_flip_limit(p);
     a.err = err_flag;
-    // one plane and at least four 16-column blocks per one-wave lane: launches with
-    // few passers ascend them in teams of waves
-    a.team_max = (p->planes == 1 && (p->n_pad + 1023) / 1024 >= UBQP_TEAM_MIN_NB) ? UBQP_TEAM_MAX_P : 0;
+    // at least four 16-column blocks per one-wave lane: launches with few passers
+    // ascend them in teams of waves
+    a.team_max = (p->n_pad + 1023) / 1024 >= UBQP_TEAM_MIN_NB ? UBQP_TEAM_MAX_P : 0;
     return a;
+}
+
+void ubqp_ascent_share_team(AscArgs &a, int group)
+{
+    if (a.team_max > 0 && group > 1) a.team_max = UBQP_TEAM_MAX_P / group > 1 ? UBQP_TEAM_MAX_P / group : 1;
 }
 
 int64_t ubqp_ascent_team_blocks(const AscArgs &a)
@@ -949,10 +990,16 @@ static hipError_t launch_team(hipStream_t st, const AscArgs &a)
 {
     const unsigned blocks = (unsigned)ubqp_ascent_team_blocks(a);
     if (blocks == 0) return hipSuccess;
-    if ((a.n_pad + 4095) / 4096 <= 1)
-        hipLaunchKernelGGL(ascent_i8_team_kernel<1>, dim3(blocks), dim3(64 * UBQP_TEAM), 0, st, a);
-    else
-        hipLaunchKernelGGL(ascent_i8_team_kernel<2>, dim3(blocks), dim3(64 * UBQP_TEAM), 0, st, a);
+    const bool two = (a.n_pad + 4095) / 4096 > 1;
+#define LT(NBT, PL) hipLaunchKernelGGL((ascent_team_kernel<NBT, PL>), dim3(blocks), dim3(64 * UBQP_TEAM), 0, st, a)
+    if (a.planes == 2) {
+        if (two) LT(2, 2);
+        else LT(1, 2);
+    } else {
+        if (two) LT(2, 1);
+        else LT(1, 1);
+    }
+#undef LT
     return hipGetLastError();
 }
 
@@ -976,16 +1023,22 @@ hipError_t ubqp_launch_ascent(hipStream_t st, const AscArgs &a)
     return hipGetLastError();
 }
 
-hipError_t ubqp_launch_ascent_team_batch(hipStream_t st, int n_pad_max, const AscArgs *args, const int64_t *prefix,
-                                         int count, int64_t blocks)
+hipError_t ubqp_launch_ascent_team_batch(hipStream_t st, int planes, int n_pad_max, const AscArgs *args,
+                                         const int64_t *prefix, int count, int64_t blocks)
 {
     if (blocks <= 0) return hipSuccess;
-    if ((n_pad_max + 4095) / 4096 <= 1)
-        hipLaunchKernelGGL(ascent_i8_team_batched<1>, dim3((unsigned)blocks), dim3(64 * UBQP_TEAM), 0, st, args, prefix,
-                           count);
-    else
-        hipLaunchKernelGGL(ascent_i8_team_batched<2>, dim3((unsigned)blocks), dim3(64 * UBQP_TEAM), 0, st, args, prefix,
-                           count);
+    const bool two = (n_pad_max + 4095) / 4096 > 1;
+#define LT(NBT, PL)                                                                                                   \
+    hipLaunchKernelGGL((ascent_team_batched<NBT, PL>), dim3((unsigned)blocks), dim3(64 * UBQP_TEAM), 0, st, args, \
+                       prefix, count)
+    if (planes == 2) {
+        if (two) LT(2, 2);
+        else LT(1, 2);
+    } else {
+        if (two) LT(2, 1);
+        else LT(1, 1);
+    }
+#undef LT
     return hipGetLastError();
 }
 
@@ -1036,7 +1089,7 @@ RelArgs ubqp_relink_args(const ubqp_problem *p, const uint64_t *elite, int64_t E
 hipError_t ubqp_launch_relink(hipStream_t st, const RelArgs &a)
 {
     if (a.P <= 0) return hipSuccess;
-    if (a.P <= UBQP_TEAM_MAX_P && (a.n_pad + 1023) / 1024 >= UBQP_TEAM_MIN_NB) {
+    if (a.P <= UBQP_RELINK_TEAM_MAX_P && (a.n_pad + 1023) / 1024 >= UBQP_TEAM_MIN_NB) {
         const unsigned blocks = (unsigned)a.P;
         const bool two = (a.n_pad + 4095) / 4096 > 1;
         if (a.planes == 2) {

@@ -91,6 +91,10 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
     for (const InstRef &r : inst) max_chunks = std::max(max_chunks, (r.pr.M + r.L.cap - 1) / r.L.cap);
     for (int64_t j = 0; j < max_chunks; j++) {
         std::map<std::pair<int, int>, Chunk> groups;
+        // instances per (planes, nb) group of this chunk offset
+        std::map<std::pair<int, int>, int> members;
+        for (const InstRef &r : inst)
+            if (r.pr.M > j * r.L.cap) members[{r.p->planes, (int)((r.p->n_pad + 1023) / 1024)}]++;
         for (const InstRef &r : inst) {
             const ubqp_problem *p = r.p;
             const ubqp_params &pr = r.pr;
@@ -103,9 +107,10 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
             int32_t *idx = r.at<int32_t>(L.oidx), *Y = r.at<int32_t>(L.Y);
             ubqp_scal *sc = r.at<ubqp_scal>(L.scal);
             const EvalArgs yr = ubqp_yrows_args(p, X, pr.M, idx, &sc->npass, off, cap, Y);
-            const AscArgs as = ubqp_ascent_args(p, X, pr.M, idx, &sc->npass, off, cap, Y, r.at<int64_t>(L.f),
-                                                pr.max_flips, r.at<int32_t>(L.flips), r.err);
+            AscArgs as = ubqp_ascent_args(p, X, pr.M, idx, &sc->npass, off, cap, Y, r.at<int64_t>(L.f),
+                                          pr.max_flips, r.at<int32_t>(L.flips), r.err);
             const int nb = ubqp_ascent_nb(as);
+            ubqp_ascent_share_team(as, members[{p->planes, nb}]);
             Chunk &ch = groups[{p->planes, nb}];
             ch.planes = p->planes;
             ch.nb = nb;
@@ -228,7 +233,7 @@ hipError_t ubqp_queue_generation(const GenTables &t, hipStream_t st, hipEvent_t 
                                  ch.yr.count(), ch.yr.total()));
         if (ae) Q(hipEventRecord(ae[2 * c], cs));
         if (ch.team.count() > 0)
-            Q(ubqp_launch_ascent_team_batch(cs, ch.n_pad_max, ch.team.d_args, ch.team.d_pre, ch.team.count(),
+            Q(ubqp_launch_ascent_team_batch(cs, ch.planes, ch.n_pad_max, ch.team.d_args, ch.team.d_pre, ch.team.count(),
                                             ch.team.total()));
         Q(ubqp_launch_ascent_batch(cs, ch.planes, ch.nb, ch.asc.d_args, ch.asc.d_pre, ch.asc.count(),
                                    ch.asc.total()));

@@ -12,11 +12,14 @@
 // Tile geometry of the int8 matrix-core contraction Y = X Q (eval_mfma.hip).
 #define UBQP_NPAD_ALIGN 128
 
-// Team ascent (one plane): a launch with at most UBQP_TEAM_MAX_P passers ascends
+// Team ascent: a launch with at most UBQP_TEAM_MAX_P passers (one per SIMD of the
+// 256-CU chip; a batched group of c instances: UBQP_TEAM_MAX_P / c each) ascends
 // each with UBQP_TEAM waves when the one-wave lane range has at least
-// UBQP_TEAM_MIN_NB blocks of 16 columns (n_pad > 3072).
+// UBQP_TEAM_MIN_NB blocks of 16 columns (n_pad > 3072).  Relinking walks at most
+// UBQP_RELINK_TEAM_MAX_P paths in teams.
 #define UBQP_TEAM 4
-#define UBQP_TEAM_MAX_P 512
+#define UBQP_TEAM_MAX_P 1024
+#define UBQP_RELINK_TEAM_MAX_P 512
 #define UBQP_TEAM_MIN_NB 4
 
 // The step-level ubqp_ascent works through passers in chunks of at most this many.
@@ -342,12 +345,15 @@ AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, con
                          int32_t *err_flag);
 int ubqp_ascent_nb(const AscArgs &a);
 int64_t ubqp_ascent_waves(const AscArgs &a);
+// A batched launch of `group` instances together: teams only while the group's
+// passers are at most UBQP_TEAM_MAX_P (each instance's bound divided by group).
+void ubqp_ascent_share_team(AscArgs &a, int group);
 // Workgroups of the team launch (0 when the launch never uses teams).
 int64_t ubqp_ascent_team_blocks(const AscArgs &a);
-// Team launch of a batched ascent group (one plane); n_pad_max: the largest n_pad
-// of the group (sets the lane range).
-hipError_t ubqp_launch_ascent_team_batch(hipStream_t st, int n_pad_max, const AscArgs *args, const int64_t *prefix,
-                                         int count, int64_t blocks);
+// Team launch of a batched ascent group (one coefficient width); n_pad_max: the
+// largest n_pad of the group (sets the lane range).
+hipError_t ubqp_launch_ascent_team_batch(hipStream_t st, int planes, int n_pad_max, const AscArgs *args,
+                                         const int64_t *prefix, int count, int64_t blocks);
 hipError_t ubqp_launch_ascent(hipStream_t st, const AscArgs &a);
 RelArgs ubqp_relink_args(const ubqp_problem *p, const uint64_t *elite, int64_t E, const int32_t *pairs, int64_t P,
                          uint64_t *X, const int32_t *Y, const int64_t *f0, int64_t *f_mid, int64_t *f_out,

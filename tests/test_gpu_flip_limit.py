@@ -28,7 +28,8 @@ def dev(a):
 
 
 @pytest.mark.parametrize("n,lo,hi", [(500, -100, 100), (700, -32768, 32767),
-                                     (4000, -100, 100)])   # a team of four waves per passer
+                                     (4000, -100, 100),       # a team of four waves per passer
+                                     (4000, -32768, 32767)])  # the same with two planes
 def test_step_ascent_reports_the_limit(ctx, n, lo, hi):
     from paper_1706_00037_amd import ubqp
     M = 32

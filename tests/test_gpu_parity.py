@@ -200,6 +200,7 @@ ASCENT_CASES = [
     (3500, 12, 2, 0.4, -100, 100, 0),     # one plane, four blocks of 16 columns per lane
     (4000, 10, 2, 0.3, -32768, 32767, 0),  # two planes, four blocks
     (3100, 10, 3, 0.5, -100, 100, 5),     # one plane, four blocks, capped
+    (7000, 1100, 2, 0.5, -32768, 32767, 0),  # two planes, 550 passers: one wave each, seven blocks
 ]
 
 
@@ -223,20 +224,26 @@ def test_ascent_matches_oracle(ctx, n, M, k, d, lo, hi, mf):
     assert (got_fl[others] == -1).all()
 
 
-@pytest.mark.parametrize("n,P,lo,hi", [(4100, 512, -100, 100),    # a team of four waves per passer
-                                       (4100, 513, -100, 100),    # one wave per passer
+@pytest.mark.parametrize("n,P,lo,hi", [(4100, 1024, -100, 100),   # a team of four waves per passer
+                                       (4100, 1025, -100, 100),   # one wave per passer
                                        (3073, 40, -3, 3),         # the smallest n_pad with teams, many ties
-                                       (8192, 64, -128, 127)])    # the widest team lanes
+                                       (8192, 64, -128, 127),     # the widest team lanes
+                                       (4100, 1024, -32768, 32767),  # two planes: a team per passer
+                                       (4100, 1025, -32768, 32767),  # two planes: one wave per passer
+                                       (3073, 40, -200, 200),     # two planes, the smallest n_pad with teams
+                                       (8192, 64, -32768, 32767)])  # two planes, the widest team lanes
 def test_ascent_team_threshold(ctx, n, P, lo, hi):
-    """Launches of at most 512 passers (n_pad > 3072, one plane) ascend each passer
-    with four waves, larger ones with one wave per passer; both give the oracle's
-    rows, values and flip counts, on either side of the threshold."""
+    """Launches of at most 1024 passers (n_pad > 3072) ascend each passer with four
+    waves, larger ones with one wave per passer; both give the oracle's rows,
+    values and flip counts, on either side of the threshold, for both coefficient
+    widths."""
     M = P + 7
     Q = make_instance(n, 0.2, lo, hi, 8000 + n + P)
     X = random_candidates(M, n, 8100 + P)
     f = oracle.eval_many(Q, X, threads=8)
     idx = np.arange(3, 3 + P, dtype=np.int32)
     prob = ctx.problem(Q)
+    assert prob.planes == (1 if -128 <= lo and hi <= 127 else 2)
     Xd, fd = dev(X), dev(f)
     fl = torch.full((M,), -1, dtype=torch.int32, device="cuda")
     ctx.ascent(prob, Xd, dev(idx), dev(np.array([P], np.int64)), fd, fl)
@@ -413,6 +420,30 @@ def test_batch_equals_alone_and_oracle(ctx):
         probs.append(ctx.problem(Q))
         params.append(dict(M=M, H=H, lam_num=lam[0], lam_den=lam[1], G=G, max_flips=mf, run_seed=40 + k))
     res = ctx.multistart_batched(probs, params)
+    for k, (prob, pr, r) in enumerate(zip(probs, params, res)):
+        alone = ctx.multistart(prob, **pr)
+        assert np.array_equal(r["stats"], alone["stats"]), k
+        assert r["best_f"] == alone["best_f"] and np.array_equal(r["best_x"], alone["best_x"]), k
+        o = oracle.multistart(Qs[k], threads=8, **pr)
+        assert np.array_equal(r["stats"], o["stats"]) and r["best_f"] == o["best_f"], k
+        assert np.array_equal(r["best_x"], o["best_x"]), k
+
+
+def test_batch_shares_the_team_bound(ctx):
+    """Three instances of one (planes, blocks) group in a batch ascend in teams only
+    while each has at most 1024 / 3 passers (alone: 1024): with lambda = 4/5, 1/2 and
+    3/10 some generations fall on either side, and every instance gives what it
+    gives alone and what the oracle gives."""
+    G = 2
+    probs, params, Qs = [], [], []
+    for k, lam in enumerate([(4, 5), (1, 2), (3, 10)]):
+        Q = make_instance(4100, 0.2, -100, 100, 7100 + k)
+        Qs.append(Q)
+        probs.append(ctx.problem(Q))
+        params.append(dict(M=1200, H=10, lam_num=lam[0], lam_den=lam[1], G=G, run_seed=50 + k))
+    res = ctx.multistart_batched(probs, params)
+    passers = np.concatenate([np.asarray(r["stats"])[:, 2] for r in res])
+    assert passers.min() <= 1024 // 3 < passers.max()
     for k, (prob, pr, r) in enumerate(zip(probs, params, res)):
         alone = ctx.multistart(prob, **pr)
         assert np.array_equal(r["stats"], alone["stats"]), k
