@@ -253,11 +253,12 @@ int ubqp_ascent(ubqp_ctx *ctx, const ubqp_problem *p, uint64_t *X_d, int64_t M, 
     UBQP_TRY(ubqp_ws_ensure(ctx, ubqp_ctx::WS_Y, (size_t)p->planes * cap * p->n_pad * sizeof(int32_t), &Y));
     for (int64_t off = 0; off < max_idx; off += cap) {
         const int64_t c = max_idx - off < cap ? max_idx - off : cap;
-        UBQP_HIP_TRY(ctx, ubqp_launch_yrows(ctx->stream,
-                                            ubqp_yrows_args(p, X_d, M, idx_d, n_idx_d, off, c, (int32_t *)Y)));
-        UBQP_HIP_TRY(ctx, ubqp_launch_ascent(ctx->stream, ubqp_ascent_args(p, X_d, M, idx_d, n_idx_d, off, c,
-                                                                           (const int32_t *)Y, f_d, max_flips,
-                                                                           flips_d, ctx->err_flag)));
+        EvalArgs yr = ubqp_yrows_args(p, X_d, M, idx_d, n_idx_d, off, c, (int32_t *)Y);
+        AscArgs as = ubqp_ascent_args(p, X_d, M, idx_d, n_idx_d, off, c, (const int32_t *)Y, f_d, max_flips, flips_d,
+                                      ctx->err_flag);
+        ubqp_split_dinit(yr, as, UBQP_SPLIT_TARGET);
+        UBQP_HIP_TRY(ctx, ubqp_launch_yrows(ctx->stream, yr));
+        UBQP_HIP_TRY(ctx, ubqp_launch_ascent(ctx->stream, as));
     }
     return UBQP_OK;
 }

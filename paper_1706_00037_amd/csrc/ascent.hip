@@ -289,7 +289,8 @@ __device__ inline void update_deltas8(int32_t &d0, int32_t &d1, int32_t &d2, int
 // T = UBQP_TEAM: the team layout of ascend_i8_team (four waves per passer, each
 // flip's best of the waves combined through LDS); T = 1: one wave.
 template <int NB, int T>
-__device__ void ascend_i16(const AscArgs &a, int64_t p, int wv, int lane, int2 (*slots)[UBQP_TEAM])
+__device__ void ascend_i16(const AscArgs &a, int64_t p, int wv, int lane, int2 (*slots)[UBQP_TEAM], int S = 1,
+                           int64_t prs = 0)
 {
     constexpr int PL = 16 * NB;
     const int vl = wv * 64 + lane;  // virtual lane
@@ -320,8 +321,13 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int wv, int lane, int2 (
         for (int t4 = 0; t4 < 4; t4++) {
             int4 v0 = {0, 0, 0, 0}, v1 = {0, 0, 0, 0}, dg = {0, 0, 0, 0};
             if (in) {
-                v0 = ubqp_ldg16i(a.Y + p * a.n_pad + col0 + 4 * t4);
-                v1 = ubqp_ldg16i(a.Y + ystride + p * a.n_pad + col0 + 4 * t4);
+                // split K (team kernels only): the sum of the S partial rows of each plane
+                for (int s = 0; s < S; s++) {
+                    const int64_t r = (p + (int64_t)s * prs) * a.n_pad + col0 + 4 * t4;
+                    const int4 u0 = ubqp_ldg16i(a.Y + r), u1 = ubqp_ldg16i(a.Y + ystride + r);
+                    v0.x += u0.x; v0.y += u0.y; v0.z += u0.z; v0.w += u0.w;
+                    v1.x += u1.x; v1.y += u1.y; v1.z += u1.z; v1.w += u1.w;
+                }
                 dg = ubqp_ldg16i(a.diag + col0 + 4 * t4);
             }
             const int32_t y0[4] = {v0.x, v0.y, v0.z, v0.w}, y1[4] = {v1.x, v1.y, v1.z, v1.w};
@@ -526,7 +532,8 @@ __global__ __launch_bounds__(64, AscOcc<NB>::waves) void ascent_i8_batched(const
 // lowest such column.  The keys and signs are those of the one-wave ascent, with
 // the key's tie-break part rewritten for the shorter lane range.
 template <int NBT>
-__device__ void ascend_i8_team(const AscArgs &a, int64_t p, int w, int lane, int2 (*slots)[UBQP_TEAM])
+__device__ void ascend_i8_team(const AscArgs &a, int64_t p, int w, int lane, int2 (*slots)[UBQP_TEAM], int S,
+                               int64_t prs)
 {
     constexpr int PLT = 16 * NBT;
     const int v = w * 64 + lane;
@@ -543,10 +550,30 @@ __device__ void ascend_i8_team(const AscArgs &a, int64_t p, int w, int lane, int
         const int col0 = v * PLT + 16 * b;
         const bool in = col0 < a.n_pad;
         const int32_t *yrow = a.Y + p * a.n_pad + col0;
+        uint32_t bits = 0;  // split K: x of the 16 columns, for keys built here
+        if (S > 1 && in && (col0 >> 6) < a.W) bits = (uint32_t)(xr[col0 >> 6] >> (col0 & 63)) & 0xFFFFu;
 #pragma unroll
         for (int t4 = 0; t4 < 4; t4++) {
             int4 y = {0, 0, 0, 0};
-            if (in) y = ubqp_ldg16i(yrow + 4 * t4);
+            if (in && S == 1) {
+                y = ubqp_ldg16i(yrow + 4 * t4);
+            } else if (in) {
+                // the S partial rows of x Q: Delta = q_jj + 2 (1 - 2 x_j) y_j, key = Delta 256 + x_j
+                int4 ys = {0, 0, 0, 0};
+                for (int s = 0; s < S; s++) {
+                    const int4 u = ubqp_ldg16i(yrow + (int64_t)s * prs * a.n_pad + 4 * t4);
+                    ys.x += u.x; ys.y += u.y; ys.z += u.z; ys.w += u.w;
+                }
+                const int4 dg = ubqp_ldg16i(a.diag + col0 + 4 * t4);
+                const int32_t yv[4] = {ys.x, ys.y, ys.z, ys.w}, dv[4] = {dg.x, dg.y, dg.z, dg.w};
+                int32_t kb[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int32_t xj = (bits >> (4 * t4 + k)) & 1u;
+                    kb[k] = (dv[k] + (xj ? -2 * yv[k] : 2 * yv[k])) * 256 + xj;
+                }
+                y = int4{kb[0], kb[1], kb[2], kb[3]};
+            }
             const int32_t kv[4] = {y.x, y.y, y.z, y.w};
             uint32_t sw = 0;
 #pragma unroll
@@ -649,10 +676,11 @@ __device__ void ascend_i8_team(const AscArgs &a, int64_t p, int w, int lane, int
 // the launch's passer count is at most UBQP_TEAM_MAX_P (the one-wave kernels take
 // the other launches and return at once here, and the other way round).
 template <int NBT, int PLANES>
-__device__ inline void ascend_team(const AscArgs &a, int64_t p, int w, int lane, int2 (*slots)[UBQP_TEAM])
+__device__ inline void ascend_team(const AscArgs &a, int64_t p, int w, int lane, int2 (*slots)[UBQP_TEAM], int S,
+                                   int64_t prs)
 {
-    if constexpr (PLANES == 1) ascend_i8_team<NBT>(a, p, w, lane, slots);
-    else ascend_i16<NBT, UBQP_TEAM>(a, p, w, lane, slots);
+    if constexpr (PLANES == 1) ascend_i8_team<NBT>(a, p, w, lane, slots, S, prs);
+    else ascend_i16<NBT, UBQP_TEAM>(a, p, w, lane, slots, S, prs);
 }
 
 template <int NBT, int PLANES>
@@ -663,7 +691,10 @@ __global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_team_kernel(AscArgs a)
     P = P < a.max_idx ? P : a.max_idx;
     if (P > a.team_max) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_team<NBT, PLANES>(a, p, w, lane, slots);
+    // split K of the Delta initialisation: S partial rows R 256 rows apart
+    const int S = ubqp_dinit_split(P, a.max_idx, a.n_pad, a.planes, a.team_max, a.split_target);
+    const int64_t prs = (P + 255) / 256 * 256;
+    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) ascend_team<NBT, PLANES>(a, p, w, lane, slots, S, prs);
 }
 
 template <int NBT, int PLANES>
@@ -678,7 +709,9 @@ __global__ __launch_bounds__(64 * UBQP_TEAM) void ascent_team_batched(const AscA
     P = P < a.max_idx ? P : a.max_idx;
     if (P > a.team_max) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int64_t p = b0; p < P; p += nb) ascend_team<NBT, PLANES>(a, p, w, lane, slots);
+    const int S = ubqp_dinit_split(P, a.max_idx, a.n_pad, a.planes, a.team_max, a.split_target);
+    const int64_t prs = (P + 255) / 256 * 256;
+    for (int64_t p = b0; p < P; p += nb) ascend_team<NBT, PLANES>(a, p, w, lane, slots, S, prs);
 }
 
 // ---- greedy path relinking -------------------------------------------------
@@ -973,6 +1006,13 @@ AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, con
     // ascend them in teams of waves
     a.team_max = (p->n_pad + 1023) / 1024 >= UBQP_TEAM_MIN_NB ? UBQP_TEAM_MAX_P : 0;
     return a;
+}
+
+void ubqp_split_dinit(EvalArgs &yr, AscArgs &as, int target)
+{
+    as.split_target = target > 0 ? target : 0;
+    yr.split_target = as.split_target;
+    yr.split_team_max = as.team_max;
 }
 
 void ubqp_ascent_share_team(AscArgs &a, int group)

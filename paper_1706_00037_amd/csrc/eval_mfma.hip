@@ -93,7 +93,31 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t total)
     return xcd * per + (xcd < rem ? xcd : rem) + j;
 }
 
-template <int EPI, int KC, int BN_, int WR_>
+// LDS of one workgroup: the double-buffered K step of Q (B) and X (A), and for the
+// key epilogue the X words of the tile's columns.  One set per (EPI, KC, BN): the
+// split and unsplit bodies of one kernel share it.
+template <int EPI, int KC, int BN> struct EvalLds {
+    static constexpr bool KEYS_LDS = EPI == EPI_KEYS && KC <= BN && BN % KC == 0;
+    static constexpr int B = BN * (KC + 16), A = BM * (KC / 64 + 1), X = KEYS_LDS ? BM * (BN / 64) : 1;
+    __device__ static int8_t (&bs())[2][B]
+    {
+        __shared__ __align__(16) int8_t v[2][B];
+        return v;
+    }
+    __device__ static uint64_t (&as())[2][A]
+    {
+        __shared__ __align__(16) uint64_t v[2][A];
+        return v;
+    }
+    __device__ static uint64_t (&xt())[X]
+    {
+        __shared__ uint64_t v[X];
+        return v;
+    }
+};
+
+// SPLIT: the Y / key epilogues' split-K body (a share of the K range, raw partial rows).
+template <int EPI, int KC, int BN_, int WR_, bool SPLIT>
 __device__ void eval_body(const EvalArgs &a, int64_t tile)
 {
     using GM = Geom<BN_, WR_>;
@@ -112,8 +136,9 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     constexpr int NSUB = KC / 32;         // 32-deep MFMA substeps per K step
     constexpr int BCH = BN * KC / 16 / THR;  // 16-byte Q chunks each thread stages per K step
     constexpr int BROWS = THR / (KC / 16);   // Q rows covered by one pass of the threads
-    __shared__ __align__(16) int8_t Bs[2][BN * BPITCH];
-    __shared__ __align__(16) uint64_t As[2][BM * APITCH];
+    auto &Bs = EvalLds<EPI, KC, BN_>::bs();
+    auto &As = EvalLds<EPI, KC, BN_>::as();
+    static_assert(sizeof(Bs[0]) == BN * BPITCH && sizeof(As[0]) == BM * APITCH * 8, "LDS layout");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / WC, wc = wave % WC;
@@ -123,7 +148,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     // tile order: n-tile-major (workgroups adjacent in t share a Q column block)
     // or m-tile-major (they share an X row block)
     int nt = a.order ? (int)(t % a.n_tiles) : (int)(t / a.m_tiles);
-    const int mt = a.order ? (int)(t / a.n_tiles) : (int)(t % a.m_tiles);
+    int mt = a.order ? (int)(t / a.n_tiles) : (int)(t % a.m_tiles);
     if (TRI) {
         // column tile nt costs nt + 1 K blocks: pair long and short tiles
         // (N-1, 0, N-2, 1, ...) so that every XCD's contiguous run of tiles holds
@@ -135,6 +160,21 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     // the row dot an optional device row count (rows beyond it are skipped)
     int64_t Mrows = a.M;
     if (STORE_Y || a.nrows_d) { const int64_t k = *a.nrows_d - a.offset; Mrows = k < a.M ? k : a.M; }
+    // Split K (few gathered rows, the team ascent consuming them): of each column
+    // tile's row-tile slots, the first S R take (part ks of the K range, row tile mt)
+    // -- slots spread over the grid like the active tiles of an unsplit launch, so
+    // over all XCDs -- and part ks stores its raw partial rows prow = ks R 256 rows
+    // further down the Y workspace.
+    int nks = 1, ks = 0;
+    int64_t prow = 0;
+    if constexpr (SPLIT) {
+        nks = ubqp_dinit_split(Mrows, a.M, a.n_pad, a.planes, a.split_team_max, a.split_target);
+        const int R = (int)((Mrows + BM - 1) / BM);
+        if (mt >= nks * R) return;
+        ks = mt / R;
+        mt -= ks * R;
+        prow = (int64_t)ks * R * BM;
+    }
     const int64_t m0 = (int64_t)mt * BM;
     if (m0 >= Mrows) return;
     const int n0 = nt * BN;
@@ -157,7 +197,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     // through the staging registers at the K steps kc = n0 / KC + s; a copy goes to
     // LDS after the loop for the epilogue (the same gathered rows, zero where the
     // staging is zero).
-    constexpr bool KEYS_LDS = EPI == EPI_KEYS && KC <= BN && BN % KC == 0;
+    constexpr bool KEYS_LDS = EvalLds<EPI, KC, BN_>::KEYS_LDS && !SPLIT;
     uint64_t xt[BN / 64] = {};
     int32_t dg[FN] = {};  // key epilogue: q_jj of the lane's columns, loaded early
     if constexpr (EPI == EPI_KEYS) {
@@ -168,7 +208,9 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
         }
     }
     const int nk_full = (a.n_pad + KC - 1) / KC;
-    const int nk = TRI ? min(nk_full, (n0 + BN + KC - 1) / KC) : nk_full;
+    // this workgroup's K steps [kb, ke)
+    const int kb = nk_full * ks / nks;
+    const int ke = TRI ? min(nk_full, (n0 + BN + KC - 1) / KC) : nk_full * (ks + 1) / nks;
     // global -> registers for K step kc; columns past n_pad (the tail of the last step) read as 0
 #define EVAL_LOAD_STAGE(kc)                                                                   \
     do {                                                                                      \
@@ -237,15 +279,16 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     _Pragma("unroll") for (int ni = 0; ni < FN; ni++)                                         \
         dst[ni] = *(const v4i *)(&Bs[buf][(wc * WTN + ni * 32 + r32) * BPITCH + 32 * (sub) + 16 * h])
 
-    EVAL_LOAD_STAGE(0);
+    EVAL_LOAD_STAGE(kb);
     EVAL_STORE_STAGE(0);
     __syncthreads();
     EVAL_READ_A(0, 0);
     EVAL_READ_B(bfc, 0, 0);
     EVAL_EXPAND_A(afc, 0);
-    for (int kc = 0; kc < nk; kc++) {
-        const int cur = kc & 1;
-        const bool more = kc + 1 < nk;
+    const int nk = ke - kb;
+    for (int kk = 0; kk < nk; kk++) {
+        const int kc = kb + kk, cur = kk & 1;
+        const bool more = kk + 1 < nk;
         if (more) EVAL_LOAD_STAGE(kc + 1);
 #pragma unroll
         for (int sub = 0; sub < NSUB; sub++) {
@@ -299,7 +342,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     // so a 64-column word lies wholly inside or wholly past n_pad; columns past n_pad
     // (only in a tile wider than the padding granularity) hold zeros and are
     // neither counted nor stored.
-    __shared__ uint64_t Xt[KEYS_LDS ? BM * (BN / 64) : 1];
+    auto &Xt = EvalLds<EPI, KC, BN_>::xt();
     if constexpr (KEYS_LDS) {
         // the staged X words of the tile's columns, for the key epilogue
 #pragma unroll
@@ -386,8 +429,9 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
                 }
             }
         }
-    } else if constexpr (EPI == EPI_Y) {
-        int32_t *Yp = a.Y + (int64_t)plane * a.M * a.n_pad;
+    } else if constexpr (EPI == EPI_Y || SPLIT) {
+        // rows of x Q per plane, or (split K) this part's raw partial rows
+        int32_t *Yp = a.Y + (int64_t)plane * a.M * a.n_pad + prow * a.n_pad;
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
 #pragma unroll
@@ -400,7 +444,7 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
                 }
             }
         }
-    } else {
+    } else if constexpr (EPI == EPI_KEYS) {
         // Ascent keys of the single-plane problem: with y = (x Q)_j and s = 1 - 2 x_j,
         // Delta_j = q_jj + 2 s y_j, key_j = Delta_j * 256 + 2 (127 - j mod PL) + x_j.
         // the key's tie-break part 2 (127 - local index in the ascent lane) per column
@@ -441,6 +485,18 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
     }
 }
 
+// The Delta initialisation splits K (ubqp_dinit_split) for this launch's device row count.
+template <int EPI> __device__ inline bool eval_split_of(const EvalArgs &a)
+{
+    if constexpr (EPI == EPI_ROWDOT) {
+        return false;
+    } else {
+        if (a.split_target <= 0) return false;
+        const int64_t k = *a.nrows_d - a.offset, P = k < a.M ? k : a.M;
+        return ubqp_dinit_split(P, a.M, a.n_pad, a.planes, a.split_team_max, a.split_target) > 1;
+    }
+}
+
 // Narrow tiles (BN = 128) with KC = 64 and 128 fit two workgroups per CU (LDS 28 /
 // 48 KB); KC = 256 (90 KB) one.  Wide tiles (BN = 256) hold 256 accumulators per
 // lane: one workgroup per CU.
@@ -449,7 +505,9 @@ template <int KC, int BN> constexpr int eval_min_blocks() { return (BN == 128 &&
 template <int EPI, int KC, int BN, int WR>
 __global__ __launch_bounds__(THR, (eval_min_blocks<KC, BN>())) void eval_kernel(EvalArgs a, int64_t total)
 {
-    eval_body<EPI, KC, BN, WR>(a, xcd_tile(blockIdx.x, total));
+    const int64_t tile = xcd_tile(blockIdx.x, total);
+    if (eval_split_of<EPI>(a)) eval_body<EPI, KC, BN, WR, true>(a, tile);
+    else eval_body<EPI, KC, BN, WR, false>(a, tile);
 }
 
 template <int EPI, int KC, int BN, int WR>
@@ -460,7 +518,8 @@ __global__ __launch_bounds__(THR, (eval_min_blocks<KC, BN>())) void eval_batched
     const int64_t t = xcd_tile(blockIdx.x, total);
     const int i = ubqp_find_inst(prefix, count, t);
     const EvalArgs a = args[i];  // a local copy: fields stay in registers across stores
-    eval_body<EPI, KC, BN, WR>(a, t - prefix[i]);
+    if (eval_split_of<EPI>(a)) eval_body<EPI, KC, BN, WR, true>(a, t - prefix[i]);
+    else eval_body<EPI, KC, BN, WR, false>(a, t - prefix[i]);
 }
 
 // f[c] = bias * popcount(X_c)^2 (the constant part of the split planes) or 0.

@@ -106,11 +106,12 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
             // the ascent takes the passers in the order list (lowest objective first)
             int32_t *idx = r.at<int32_t>(L.oidx), *Y = r.at<int32_t>(L.Y);
             ubqp_scal *sc = r.at<ubqp_scal>(L.scal);
-            const EvalArgs yr = ubqp_yrows_args(p, X, pr.M, idx, &sc->npass, off, cap, Y);
+            EvalArgs yr = ubqp_yrows_args(p, X, pr.M, idx, &sc->npass, off, cap, Y);
             AscArgs as = ubqp_ascent_args(p, X, pr.M, idx, &sc->npass, off, cap, Y, r.at<int64_t>(L.f),
                                           pr.max_flips, r.at<int32_t>(L.flips), r.err);
             const int nb = ubqp_ascent_nb(as);
             ubqp_ascent_share_team(as, members[{p->planes, nb}]);
+            ubqp_split_dinit(yr, as, UBQP_SPLIT_TARGET / members[{p->planes, nb}]);
             Chunk &ch = groups[{p->planes, nb}];
             ch.planes = p->planes;
             ch.nb = nb;

@@ -101,9 +101,12 @@ extern "C" int ubqp_relink(ubqp_ctx *ctx, const ubqp_problem *p, const uint64_t 
                                                                   ctx->err_flag)));
         hipLaunchKernelGGL(rl_list, dim3(1), dim3(THR), 0, st, steps_d + off, c, list, count);
         UBQP_HIP_TRY(ctx, hipGetLastError());
-        UBQP_HIP_TRY(ctx, ubqp_launch_yrows(st, ubqp_yrows_args(p, X, c, list, count, 0, c, (int32_t *)Y)));
-        UBQP_HIP_TRY(ctx, ubqp_launch_ascent(st, ubqp_ascent_args(p, X, c, list, count, 0, c, (const int32_t *)Y,
-                                                                  f_out_d + off, max_flips, flips, ctx->err_flag)));
+        EvalArgs yr = ubqp_yrows_args(p, X, c, list, count, 0, c, (int32_t *)Y);
+        AscArgs as = ubqp_ascent_args(p, X, c, list, count, 0, c, (const int32_t *)Y, f_out_d + off, max_flips,
+                                      flips, ctx->err_flag);
+        ubqp_split_dinit(yr, as, UBQP_SPLIT_TARGET);
+        UBQP_HIP_TRY(ctx, ubqp_launch_yrows(st, yr));
+        UBQP_HIP_TRY(ctx, ubqp_launch_ascent(st, as));
     }
     return UBQP_OK;
 }

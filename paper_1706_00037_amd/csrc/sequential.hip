@@ -379,9 +379,10 @@ extern "C" int ubqp_sequential(ubqp_ctx *ctx, const ubqp_problem *p, const ubqp_
     EvalArgs ev = ubqp_eval_args(p, a.X, B, a.f);
     ev.nrows_d = &a.st->valid;
     const int variant = ubqp_eval_variant_for(p, B);
-    const EvalArgs yr = ubqp_yrows_args(p, a.X, B, a.idx, &a.st->npass, 0, B, Y);
-    const AscArgs as = ubqp_ascent_args(p, a.X, B, a.idx, &a.st->npass, 0, B, Y, a.f, sp->max_flips, a.flips,
-                                        ctx->err_flag);
+    EvalArgs yr = ubqp_yrows_args(p, a.X, B, a.idx, &a.st->npass, 0, B, Y);
+    AscArgs as = ubqp_ascent_args(p, a.X, B, a.idx, &a.st->npass, 0, B, Y, a.f, sp->max_flips, a.flips,
+                                  ctx->err_flag);
+    ubqp_split_dinit(yr, as, UBQP_SPLIT_TARGET);
     const bool use_graph = !(sp->flags & UBQP_NO_GRAPH);
     if (use_graph) {
         UBQP_HIP_TRY(ctx, hipStreamCreateWithFlags(&run.cap, hipStreamNonBlocking));

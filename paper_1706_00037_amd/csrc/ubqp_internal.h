@@ -203,7 +203,8 @@ struct EvalArgs {            // int8 matrix-core contraction Y = X Q and its epi
     int32_t keys_pl;         // keys: columns per lane of the ascent (16 NB)
     int64_t bias;            // eval_init: f starts at bias * popcount(x)^2
     int32_t order;           // tile order: 0 n-tile-major, 1 m-tile-major (an eval variant choice)
-    int32_t pad_;
+    int32_t split_target;    // Y / key epilogues: split K below this many workgroups (0: never)
+    int64_t split_team_max;  // ... and only while the ascent takes the rows in teams (its team_max)
 };
 
 struct ScreenArgs {          // exact T(lambda) screening
@@ -241,7 +242,36 @@ struct AscArgs {             // steepest 1-flip ascent
     int32_t max_flips, safety_cap;
     int32_t *err;
     int64_t team_max;        // launches with at most this many passers ascend them in teams (0: never)
+    int32_t split_target;    // the Delta initialisation's split target (ubqp_dinit_split)
+    int32_t pad_;
 };
+
+// Split K of the Delta initialisation.  A launch with few passers has few row tiles
+// of 256: fewer workgroups than the chip holds.  While the team ascent takes the
+// passers (P <= team_max), S workgroups share each tile's K range (K steps of 128)
+// and store raw partial rows of x Q, partial s of row r at row s R 256 + r of the Y
+// workspace (R = ceil(P / 256) row tiles, per plane); the team kernels sum the S
+// partials when they load a passer.  Both sides take S from this function of the
+// device passer count.  S x (active tiles) stays near `target` workgroups, the
+// partials inside the workspace's cap rows, and the tiles inside the launch's grid
+// (cap / 256 rounded up, times the column tiles and planes).
+#define UBQP_SPLIT_TARGET 512
+#define UBQP_SPLIT_MAX 8
+__host__ __device__ inline int ubqp_dinit_split(int64_t P, int64_t cap, int n_pad, int planes, int64_t team_max,
+                                                int target)
+{
+    if (P <= 0 || P > cap || P > team_max || target <= 0) return 1;
+    const int64_t R = (P + 255) / 256, nk = n_pad / 128;
+    const int64_t A = R * nk * planes;  // active tiles: row tiles x column tiles of 128 x planes
+    if (A >= target) return 1;
+    int64_t S = (target + A - 1) / A;
+    S = S < UBQP_SPLIT_MAX ? S : UBQP_SPLIT_MAX;
+    S = S < nk ? S : nk;
+    const int64_t fit = (cap - P) / (R * 256) + 1, grid = ((cap + 255) / 256) / R;
+    S = S < fit ? S : fit;
+    S = S < grid ? S : grid;
+    return S < 1 ? 1 : (int)S;
+}
 
 struct RelArgs {             // greedy path relinking, one wave per path
     const void *qa;          // ascent matrix (zero diagonal), int8 or int16 [n_pad][ncol_a]
@@ -345,6 +375,10 @@ AscArgs ubqp_ascent_args(const ubqp_problem *p, uint64_t *X, int64_t x_rows, con
                          int32_t *err_flag);
 int ubqp_ascent_nb(const AscArgs &a);
 int64_t ubqp_ascent_waves(const AscArgs &a);
+// Let the Delta initialisation yr split K (ubqp_dinit_split) for the ascent as that
+// consumes its rows: both take the split from the same device passer count, target
+// and team bound (call after ubqp_ascent_share_team).
+void ubqp_split_dinit(EvalArgs &yr, AscArgs &as, int target);
 // A batched launch of `group` instances together: teams only while the group's
 // passers are at most UBQP_TEAM_MAX_P (each instance's bound divided by group).
 void ubqp_ascent_share_team(AscArgs &a, int group);

@@ -254,6 +254,34 @@ def test_ascent_team_threshold(ctx, n, P, lo, hi):
     assert np.array_equal(fl.cpu().numpy()[idx], flo[idx])
 
 
+@pytest.mark.parametrize("n,P,lo,hi", [(4100, 1, -100, 100),      # one passer: the K range in 8 parts
+                                       (4100, 300, -100, 100),    # 2 row tiles
+                                       (8192, 700, -128, 127),    # 3 row tiles, 64 column tiles: 3 parts
+                                       (3073, 40, -3, 3),         # many ties
+                                       (4100, 40, -32768, 32767),  # two planes: partial rows per plane
+                                       (8192, 260, -32768, 32767)])
+def test_ascent_split_delta_init(ctx, n, P, lo, hi):
+    """Few passers in a list with room to spare: the Delta initialisation splits its
+    K range over several workgroups per tile and the team ascent sums the partial
+    rows; rows, values and flip counts are the oracle's."""
+    cap = 4096
+    M = P + 5
+    Q = make_instance(n, 0.3, lo, hi, 8200 + n + P)
+    X = random_candidates(M, n, 8300 + P)
+    f = oracle.eval_many(Q, X, threads=8)
+    idx = np.full(cap, -1, np.int32)
+    idx[:P] = np.arange(5, 5 + P, dtype=np.int32)[::-1]
+    prob = ctx.problem(Q)
+    Xd, fd = dev(X), dev(f)
+    fl = torch.full((M,), -1, dtype=torch.int32, device="cuda")
+    ctx.ascent(prob, Xd, dev(idx), dev(np.array([P], np.int64)), fd, fl)
+    ctx.sync()
+    Xo, fo, flo = oracle.ascent_many(Q, X, idx[:P], f, threads=8)
+    assert np.array_equal(host_u64(Xd), Xo)
+    assert np.array_equal(fd.cpu().numpy(), fo)
+    assert np.array_equal(fl.cpu().numpy()[idx[:P]], flo[idx[:P]])
+
+
 def test_ascent_device_count_below_capacity(ctx):
     """Only the first *n_idx_d listed rows are ascended."""
     n, M = 300, 40
