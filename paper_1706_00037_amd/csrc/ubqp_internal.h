@@ -13,12 +13,13 @@
 #define UBQP_NPAD_ALIGN 128
 
 // Team ascent: a launch with at most UBQP_TEAM_MAX_P passers (one per SIMD of the
-// 256-CU chip; a batched group of c instances: UBQP_TEAM_MAX_P / c each) ascends
-// each with UBQP_TEAM waves when the one-wave lane range has at least
-// UBQP_TEAM_MIN_NB blocks of 16 columns (n_pad > 3072).  Relinking walks at most
-// UBQP_RELINK_TEAM_MAX_P paths in teams.
+// 256-CU chip; two planes: UBQP_TEAM_MAX_P_I16; a batched group of c instances:
+// the bound / c each) ascends each with UBQP_TEAM waves when the one-wave lane
+// range has at least UBQP_TEAM_MIN_NB blocks of 16 columns (n_pad > 3072).
+// Relinking walks at most UBQP_RELINK_TEAM_MAX_P paths in teams.
 #define UBQP_TEAM 4
 #define UBQP_TEAM_MAX_P 1024
+#define UBQP_TEAM_MAX_P_I16 512
 #define UBQP_RELINK_TEAM_MAX_P 512
 #define UBQP_TEAM_MIN_NB 4
 

@@ -228,13 +228,13 @@ def test_ascent_matches_oracle(ctx, n, M, k, d, lo, hi, mf):
                                        (4100, 1025, -100, 100),   # one wave per passer
                                        (3073, 40, -3, 3),         # the smallest n_pad with teams, many ties
                                        (8192, 64, -128, 127),     # the widest team lanes
-                                       (4100, 1024, -32768, 32767),  # two planes: a team per passer
-                                       (4100, 1025, -32768, 32767),  # two planes: one wave per passer
+                                       (4100, 512, -32768, 32767),  # two planes (bound 512): a team per passer
+                                       (4100, 513, -32768, 32767),  # two planes: one wave per passer
                                        (3073, 40, -200, 200),     # two planes, the smallest n_pad with teams
                                        (8192, 64, -32768, 32767)])  # two planes, the widest team lanes
 def test_ascent_team_threshold(ctx, n, P, lo, hi):
-    """Launches of at most 1024 passers (n_pad > 3072) ascend each passer with four
-    waves, larger ones with one wave per passer; both give the oracle's rows,
+    """Launches of at most 1024 passers (two planes: 512; n_pad > 3072) ascend each
+    passer with four waves, larger ones with one wave per passer; both give the oracle's rows,
     values and flip counts, on either side of the threshold, for both coefficient
     widths."""
     M = P + 7
