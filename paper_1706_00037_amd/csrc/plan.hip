@@ -110,7 +110,7 @@ void GenTables::build(const std::vector<InstRef> &inst, const std::vector<char> 
             AscArgs as = ubqp_ascent_args(p, X, pr.M, idx, &sc->npass, off, cap, Y, r.at<int64_t>(L.f),
                                           pr.max_flips, r.at<int32_t>(L.flips), r.err);
             const int nb = ubqp_ascent_nb(as);
-            ubqp_ascent_share_team(as, members[{p->planes, nb}]);
+            ubqp_ascent_share_team(as, members[{p->planes, nb}], (int)inst.size());
             ubqp_split_dinit(yr, as, UBQP_SPLIT_TARGET / members[{p->planes, nb}]);
             Chunk &ch = groups[{p->planes, nb}];
             ch.planes = p->planes;

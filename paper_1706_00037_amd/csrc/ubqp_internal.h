@@ -13,13 +13,14 @@
 #define UBQP_NPAD_ALIGN 128
 
 // Team ascent: a launch with at most UBQP_TEAM_MAX_P passers (one per SIMD of the
-// 256-CU chip; two planes: UBQP_TEAM_MAX_P_I16; a batched group of c instances:
-// the bound / c each) ascends each with UBQP_TEAM waves when the one-wave lane
-// range has at least UBQP_TEAM_MIN_NB blocks of 16 columns (n_pad > 3072).
-// Relinking walks at most UBQP_RELINK_TEAM_MAX_P paths in teams.
+// 256-CU chip; two planes: UBQP_TEAM_MAX_P_I16; a launch table of several instances:
+// at most UBQP_TEAM_MAX_P_GROUP / c each, c the instances of the (planes, NB) group) ascends each with UBQP_TEAM waves when the
+// one-wave lane range has at least UBQP_TEAM_MIN_NB blocks of 16 columns
+// (n_pad > 3072).  Relinking walks at most UBQP_RELINK_TEAM_MAX_P paths in teams.
 #define UBQP_TEAM 4
 #define UBQP_TEAM_MAX_P 1024
 #define UBQP_TEAM_MAX_P_I16 512
+#define UBQP_TEAM_MAX_P_GROUP 512
 #define UBQP_RELINK_TEAM_MAX_P 512
 #define UBQP_TEAM_MIN_NB 4
 
@@ -380,9 +381,10 @@ int64_t ubqp_ascent_waves(const AscArgs &a);
 // consumes its rows: both take the split from the same device passer count, target
 // and team bound (call after ubqp_ascent_share_team).
 void ubqp_split_dinit(EvalArgs &yr, AscArgs &as, int target);
-// A batched launch of `group` instances together: teams only while the group's
-// passers are at most UBQP_TEAM_MAX_P (each instance's bound divided by group).
-void ubqp_ascent_share_team(AscArgs &a, int group);
+// A launch table of `instances` instances (a batch or the server's active requests),
+// `group` of them in this ascent's (planes, NB) group: with more than one instance,
+// teams only while each has at most UBQP_TEAM_MAX_P_GROUP / group passers.
+void ubqp_ascent_share_team(AscArgs &a, int group, int instances);
 // Workgroups of the team launch (0 when the launch never uses teams).
 int64_t ubqp_ascent_team_blocks(const AscArgs &a);
 // Team launch of a batched ascent group (one coefficient width); n_pad_max: the
