@@ -195,6 +195,11 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         const int local = 127 - ((bk >> 1) & 127);
         const int32_t xk = bk & 1;              // x_k before the flip
         const int K = asc_col0<NB>(lstar, local >> 4) + (local & 15);
+        // row k is read first: its latency is the flip's critical path
+        const int8_t *row = qa + (int64_t)K * a.ncol_a;
+        uint4 w[NB];
+#pragma unroll
+        for (int b = 0; b < NB; b++) w[b] = ubqp_ldg16(row + asc_col0<NB>(lane, b));
         const int bs = local >> 4, ts = local & 15;
         // the flipped variable: Delta_k -> -V, x_k and s_k toggle (lane lstar only)
         const bool own = lane == lstar;
@@ -213,10 +218,6 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         flips++;
         // Delta_i += 2 d s_i q_ik for i != k, with d = 1 - 2 x_k: key_i += (q_ik s_i) * 512 d
         const int32_t step = xk ? -512 : 512;
-        const int8_t *row = qa + (int64_t)K * a.ncol_a;
-        uint4 w[NB];
-#pragma unroll
-        for (int b = 0; b < NB; b++) w[b] = ubqp_ldg16(row + asc_col0<NB>(lane, b));
         // the update is the VALU burst of a flip; with the wave's priority raised
         // while it runs, the SIMD's other wave fills the gaps its loads leave
         // rather than stretching it
@@ -408,6 +409,22 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int wv, int lane, int2 (
             xk = (win.y >> 30) & 1;
             own = vl == K / PL;
         }
+        // row k, read first (its latency is the flip's critical path) except by one
+        // wave at NB >= 7, whose registers cannot hold the row across the flipped
+        // column's update
+        const int16_t *row = qa + (int64_t)K * a.ncol_a + col_base;
+        uint4 w[NB][2];
+        auto read_row = [&]() {
+            // a team's virtual lanes can reach past the row's ncol_a columns
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                const bool in = T == 1 || col_base + 16 * b < a.ncol_a;
+                w[b][0] = in ? ubqp_ldg16(row + 16 * b) : uint4{0u, 0u, 0u, 0u};
+                w[b][1] = in ? ubqp_ldg16(row + 16 * b + 8) : uint4{0u, 0u, 0u, 0u};
+            }
+        };
+        constexpr bool EARLY = T > 1 || NB <= 6;
+        if constexpr (EARLY) read_row();
         const int bs_k = (K % PL) >> 4, ts_k = K & 15;
         const uint32_t sflip = own ? 0xFEu << (8 * (ts_k & 3)) : 0u;
 #pragma unroll
@@ -423,15 +440,7 @@ __device__ void ascend_i16(const AscArgs &a, int64_t p, int wv, int lane, int2 (
         flips++;
         // Delta_i += 2 d s_i q_ik for i != k, d = 1 - 2 x_k (the ascent matrix has q_kk = 0)
         const int32_t step = xk ? -2 : 2;
-        const int16_t *row = qa + (int64_t)K * a.ncol_a + col_base;
-        uint4 w[NB][2];
-        // a team's virtual lanes can reach past the row's ncol_a columns
-#pragma unroll
-        for (int b = 0; b < NB; b++) {
-            const bool in = T == 1 || col_base + 16 * b < a.ncol_a;
-            w[b][0] = in ? ubqp_ldg16(row + 16 * b) : uint4{0u, 0u, 0u, 0u};
-            w[b][1] = in ? ubqp_ldg16(row + 16 * b + 8) : uint4{0u, 0u, 0u, 0u};
-        }
+        if constexpr (!EARLY) read_row();
         __builtin_amdgcn_s_setprio(1);  // as in the int8 ascent
 #pragma unroll
         for (int b = 0; b < NB; b++) {
@@ -615,6 +624,14 @@ __device__ void ascend_i8_team(const AscArgs &a, int64_t p, int w, int lane, int
         V = win.x;
         if (V <= 0 || flips >= cap) break;
         const int K = win.y & 0x3FFFFFFF;
+        // row k is read first: its latency is the flip's critical path
+        const int8_t *row = qa + (int64_t)K * a.ncol_a;
+        uint4 wr[NBT];
+#pragma unroll
+        for (int b = 0; b < NBT; b++) {
+            const int col0 = v * PLT + 16 * b;
+            wr[b] = col0 < a.ncol_a ? ubqp_ldg16(row + col0) : uint4{0u, 0u, 0u, 0u};
+        }
         const int32_t xk = (win.y >> 30) & 1;
         const int vk = K / PLT, local = K - vk * PLT;
         const int bs = local >> 4, ts = local & 15;
@@ -633,13 +650,6 @@ __device__ void ascend_i8_team(const AscArgs &a, int64_t p, int w, int lane, int
         gain += V;
         flips++;
         const int32_t step = xk ? -512 : 512;
-        const int8_t *row = qa + (int64_t)K * a.ncol_a;
-        uint4 wr[NBT];
-#pragma unroll
-        for (int b = 0; b < NBT; b++) {
-            const int col0 = v * PLT + 16 * b;
-            wr[b] = col0 < a.ncol_a ? ubqp_ldg16(row + col0) : uint4{0u, 0u, 0u, 0u};
-        }
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int b = 0; b < NBT; b++) {
@@ -864,6 +874,24 @@ __device__ void relink_path(const RelArgs &a, int64_t p, int wv, int lane, int2 
             xk = (win.y >> 30) & 1;
             own = vl == K / PL;
         }
+        // row k is read first: its latency is the step's critical path (a team's
+        // virtual lanes can reach past the row's ncol_a columns)
+        uint4 w1[PLANES == 1 ? NB : 1];
+        uint4 w2[PLANES == 2 ? NB : 1][2];
+        if constexpr (PLANES == 1) {
+            const int8_t *row = (const int8_t *)a.qa + (int64_t)K * a.ncol_a + col_base;
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+                w1[b] = (T == 1 || col_base + 16 * b < a.ncol_a) ? ubqp_ldg16(row + 16 * b) : uint4{0u, 0u, 0u, 0u};
+        } else {
+            const int16_t *row = (const int16_t *)a.qa + (int64_t)K * a.ncol_a + col_base;
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                const bool in = T == 1 || col_base + 16 * b < a.ncol_a;
+                w2[b][0] = in ? ubqp_ldg16(row + 16 * b) : uint4{0u, 0u, 0u, 0u};
+                w2[b][1] = in ? ubqp_ldg16(row + 16 * b + 8) : uint4{0u, 0u, 0u, 0u};
+            }
+        }
         const int bs_k = (K % PL) >> 4, ts_k = K & 15;
         const uint32_t sflip = own ? 0xFEu << (8 * (ts_k & 3)) : 0u;
 #pragma unroll
@@ -886,42 +914,29 @@ __device__ void relink_path(const RelArgs &a, int64_t p, int wv, int lane, int2 
         }
         // Delta_i += 2 d s_i q_ik for i != k, d = 1 - 2 x_k (the ascent matrix has q_kk = 0)
         const int32_t step = xk ? -2 : 2;
-        if (PLANES == 1) {
-            const int8_t *row = (const int8_t *)a.qa + (int64_t)K * a.ncol_a + col_base;
-            uint4 w[NB];
-            // a team's virtual lanes can reach past the row's ncol_a columns
-#pragma unroll
-            for (int b = 0; b < NB; b++)
-                w[b] = (T == 1 || col_base + 16 * b < a.ncol_a) ? ubqp_ldg16(row + 16 * b) : uint4{0u, 0u, 0u, 0u};
+        if constexpr (PLANES == 1) {
 #pragma unroll
             for (int b = 0; b < NB; b++) {
                 int32_t d[16];
 #pragma unroll
                 for (int t = 0; t < 16; t++) d[t] = dl[b][t];
-                update_keys8(d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], w[b].x, w[b].y, ss[b][0], ss[b][1], step);
-                update_keys8(d[8], d[9], d[10], d[11], d[12], d[13], d[14], d[15], w[b].z, w[b].w, ss[b][2],
+                update_keys8(d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], w1[b].x, w1[b].y, ss[b][0], ss[b][1],
+                             step);
+                update_keys8(d[8], d[9], d[10], d[11], d[12], d[13], d[14], d[15], w1[b].z, w1[b].w, ss[b][2],
                              ss[b][3], step);
 #pragma unroll
                 for (int t = 0; t < 16; t++) dl[b][t] = d[t];
             }
         } else {
-            const int16_t *row = (const int16_t *)a.qa + (int64_t)K * a.ncol_a + col_base;
-            uint4 w[NB][2];
-#pragma unroll
-            for (int b = 0; b < NB; b++) {
-                const bool in = T == 1 || col_base + 16 * b < a.ncol_a;
-                w[b][0] = in ? ubqp_ldg16(row + 16 * b) : uint4{0u, 0u, 0u, 0u};
-                w[b][1] = in ? ubqp_ldg16(row + 16 * b + 8) : uint4{0u, 0u, 0u, 0u};
-            }
 #pragma unroll
             for (int b = 0; b < NB; b++) {
                 int32_t d[16];
 #pragma unroll
                 for (int t = 0; t < 16; t++) d[t] = dl[b][t];
-                update_deltas8(d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], w[b][0].x, w[b][0].y, w[b][0].z,
-                               w[b][0].w, ss[b][0], ss[b][1], step);
-                update_deltas8(d[8], d[9], d[10], d[11], d[12], d[13], d[14], d[15], w[b][1].x, w[b][1].y,
-                               w[b][1].z, w[b][1].w, ss[b][2], ss[b][3], step);
+                update_deltas8(d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], w2[b][0].x, w2[b][0].y, w2[b][0].z,
+                               w2[b][0].w, ss[b][0], ss[b][1], step);
+                update_deltas8(d[8], d[9], d[10], d[11], d[12], d[13], d[14], d[15], w2[b][1].x, w2[b][1].y,
+                               w2[b][1].z, w2[b][1].w, ss[b][2], ss[b][3], step);
 #pragma unroll
                 for (int t = 0; t < 16; t++) dl[b][t] = d[t];
             }
