@@ -15,8 +15,8 @@ oracle wrote (tests/golden/make_full_size.py; nothing in them comes from the GPU
 * the first 64 requests of the serving workload through the request server, all
   submitted at once so that they share generations, and every other request with
   n <= 1500 of the serving bench's 2100-request trace: statistics and incumbents;
-* one generation at n = 8192, M = 70000, lambda = 0: more passers than one Delta
-  workspace holds, ascended in two chunks.
+* one generation at n = 8192, M = 70000, lambda = 0, ascents capped at 32 flips:
+  more passers than one Delta workspace holds, ascended in two chunks.
 Launch configuration: the one bench.py times (graph-replayed generations, the
 default evaluation variant, or the autotuned one where the bench tunes).
 """
