@@ -118,15 +118,19 @@ template <int NB> __device__ inline int32_t lane_max(const v16i (&kk)[NB])
 }
 
 // Largest value over the wave (DPP within rows of 16, then across rows by row broadcasts).
+// Lanes a step does not write (the rows outside a broadcast's row mask) take
+// INT32_MIN, the identity of max, so each step compiles to one v_max_i32 with a DPP
+// operand rather than a copy, a DPP move and a maximum.
 __device__ inline int32_t wave_max_i32(int32_t v)
 {
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    constexpr int32_t LO = INT32_MIN;
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x128, 0xF, 0xF, false));  // row_ror:8
     // every lane holds its row's maximum; fold the rows into the last one
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15 into rows 1, 3
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31 into rows 2, 3
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x142, 0xA, 0xF, false));  // row_bcast:15 into rows 1, 3
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x143, 0xC, 0xF, false));  // row_bcast:31 into rows 2, 3
     return __builtin_amdgcn_readlane(v, 63);
 }
 
