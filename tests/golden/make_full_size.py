@@ -21,6 +21,12 @@ the GPU library.  Each case is one JSON file under ``tests/golden/full_size/``:
   ms_n8192_M70000_multichunk  one generation at n = 8192, density 0.05, M = 70000,
                            lambda = 0, ascents capped at 32 flips: more passers than one
                            Delta workspace holds
+  ms_n7000_M16384_blend_G3 the headline workload with blending diversification
+                           (the bench's blend leg), 3 generations
+  seq_n7000_I2500          the loop of Fig. 2 on the headline instance, 2500
+                           iterations, Mean over 1000 samples, lambda = 1/2 (the bench's
+                           sequential leg): its statistics, replacement history, final
+                           solution and the SHA-256 of every iteration's objective
 
 A multi-start case records, per generation, the screen statistics {Sum, Max,
 passers, flips, incumbent} and the SHA-256 of every candidate's objective before
@@ -73,8 +79,8 @@ def write(name: str, obj: dict):
     os.replace(tmp, os.path.join(OUT, name + ".json"))
 
 
-def multistart_record(Q, params: dict, threads: int, dump: bool = True) -> dict:
-    o = oracle.multistart(Q, threads=threads, dump=dump, **params)
+def multistart_record(Q, params: dict, threads: int, dump: bool = True, flags: int = 0) -> dict:
+    o = oracle.multistart(Q, threads=threads, dump=dump, flags=flags, **params)
     rec = dict(params=params, best_f=o["best_f"], have_best=o["have_best"],
                best_x=words_hex(o["best_x"]), stats=o["stats"].tolist())
     if dump:
@@ -159,6 +165,27 @@ def case_multichunk(threads: int):
     write("ms_n8192_M70000_multichunk", rec)
 
 
+def case_blend7000(threads: int):
+    c = WORKLOADS["n7000_d0.50_M16384"]
+    Q = make_instance(c["n"], c["density"], c["lo"], c["hi"], c["inst_seed"])
+    params = dict(M=c["M"], H=c["H"], lam_num=1, lam_den=2, G=3, run_seed=c["run_seed"])
+    rec = multistart_record(Q, params, threads, flags=oracle.FLAG_BLEND)
+    rec.update(workload="n7000_d0.50_M16384", blend=True)
+    write("ms_n7000_M16384_blend_G3", rec)
+
+
+def case_seq7000(threads: int):
+    c = WORKLOADS["n7000_d0.50_M16384"]
+    Q = make_instance(c["n"], c["density"], c["lo"], c["hi"], c["inst_seed"])
+    params = dict(iterations=2500, samples=1000, lam_num=1, lam_den=2, run_seed=c["run_seed"])
+    o = oracle.sequential(Q, H=c["n"], threads=threads, **params)
+    rec = {k: (int(o[k]) if k != "have_best" else bool(o[k]))
+           for k in ("best_f", "have_best", "sample_sum", "start_f", "passers", "flips", "improvements")}
+    rec.update(workload="n7000_d0.50_M16384", params=params, history=o["history"].tolist(),
+               best_x=words_hex(o["best_x"]), f_sha256=digest(o["f_dump"]))
+    write("seq_n7000_I2500", rec)
+
+
 CASES = {
     "eval": case_eval,
     "ms2500": lambda th: case_multistart("n2500_d0.10_M65536", 20, (1, 2), "ms_n2500_M65536_G20", th),
@@ -169,6 +196,8 @@ CASES = {
     "serve": case_serve,
     "serve_small": case_serve_small,
     "multichunk": case_multichunk,
+    "blend7000": case_blend7000,
+    "seq7000": case_seq7000,
 }
 
 

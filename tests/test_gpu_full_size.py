@@ -16,7 +16,12 @@ oracle wrote (tests/golden/make_full_size.py; nothing in them comes from the GPU
   submitted at once so that they share generations, and every other request with
   n <= 1500 of the serving bench's 2100-request trace: statistics and incumbents;
 * one generation at n = 8192, M = 70000, lambda = 0, ascents capped at 32 flips:
-  more passers than one Delta workspace holds, ascended in two chunks.
+  more passers than one Delta workspace holds, ascended in two chunks;
+* the headline workload with blending diversification over three generations, as
+  the multi-start runs above;
+* the loop of Fig. 2 one candidate per iteration on the headline instance, 2500
+  iterations: its statistics, the history of incumbent replacements, the final
+  solution and every iteration's objective (SHA-256 of the dump).
 Launch configuration: the one bench.py times (graph-replayed generations, the
 default evaluation variant, or the autotuned one where the bench tunes).
 """
@@ -84,12 +89,12 @@ def test_eval_every_objective_n7000(ctx, q7000):
     assert digest(f) == g["f_sha256"]
 
 
-def _check_run(ctx, Q, g):
+def _check_run(ctx, Q, g, flags=0):
     p = g["params"]
     G, M = p["G"], p["M"]
     prob = ctx.problem(Q)
     dump = torch.zeros(G * M, dtype=torch.int64, device="cuda")
-    r = ctx.multistart(prob, f_dump=dump, **p)
+    r = ctx.multistart(prob, f_dump=dump, flags=flags, **p)
     fd = dump.cpu().numpy().reshape(G, M)
     for gen in range(G):
         assert digest(fd[gen]) == g["f_sha256"][gen], f"objectives of generation {gen} differ"
@@ -110,6 +115,29 @@ def test_multistart_n2500_M65536_G20(ctx):
 @pytest.mark.parametrize("lam", ["3_10", "1_2", "4_5"])
 def test_multistart_n7000_M16384_each_lambda(ctx, q7000, lam):
     _check_run(ctx, q7000, golden(f"ms_n7000_M16384_lam{lam}_G3"))
+
+
+@pytest.mark.timeout(600)
+def test_multistart_n7000_M16384_blend(ctx, q7000):
+    from paper_1706_00037_amd import ubqp
+    g = golden("ms_n7000_M16384_blend_G3")
+    assert g["blend"]
+    _check_run(ctx, q7000, g, flags=ubqp.UBQP_BLEND)
+
+
+@pytest.mark.timeout(600)
+def test_sequential_n7000_I2500(ctx, q7000):
+    g = golden("seq_n7000_I2500")
+    p = g["params"]
+    fd = torch.full((p["iterations"],), 7, dtype=torch.int64, device="cuda")
+    r = ctx.sequential(ctx.problem(q7000), H=0, f_dump=fd, **p)
+    torch.cuda.synchronize()
+    for k in ("best_f", "have_best", "sample_sum", "start_f", "passers", "flips", "improvements"):
+        assert r[k] == g[k], k
+    assert r["iterations_done"] == p["iterations"]
+    assert r["history"].tolist() == g["history"]
+    assert np.array_equal(r["best_x"], words(g["best_x"]))
+    assert digest(fd.cpu().numpy()) == g["f_sha256"]
 
 
 def _same_as_golden(r, g, tag):
