@@ -8,17 +8,19 @@
 // matrix", built once at upload) so the row update leaves Delta_k to the
 // explicit negation.
 //
-// int8 Q (ascent_i8): lane l owns the contiguous columns [l PL, (l+1) PL),
-// PL = 16 NB, and keeps for each of them the 32-bit key
-//     key_i = Delta_i * 256 + 2 (127 - local_i) + x_i     (|Delta_i| < 2^21)
+// int8 Q (ascent_i8): lane l owns the columns 1024 b + 16 l + t (block b < NB,
+// t < 16), so each 16-byte row load of the wave is one contiguous KB, and keeps
+// for each of them the 32-bit key
+//     key_i = Delta_i * 256 + 32 (7 - b) + 2 (15 - t) + x_i     (|Delta_i| < 2^21)
 // and the sign s_i as a signed byte (four per VGPR).  A flip is
 //     key_i += (q_ik * s_i) * 512 d  -- one SDWA v_mul_i32_i24 (byte x byte,
 //                                       both sign-extended) and one v_mad_i32_i24
-// with 512 d in an SGPR, so the lane's best key is a v_max3 tree, the wave's best
-// Delta one DPP max, and the lowest column attaining it the lowest such lane
-// (ballot + ffs) with its local index and old x_k read from the key.  The flipped
-// variable's key and sign are rewritten through one uniform-indexed register
-// access per block.
+// with 512 d in an SGPR, so the lane's best key is a v_max3 tree (the largest
+// Delta, then the lowest block, then the lowest t), the wave's best (Delta, block)
+// one DPP max of key >> 5, and the lowest column attaining the largest Delta the
+// lowest lane attaining that pair (ballot + ffs), with t and the old x_k read from
+// its key.  The flipped variable's key and sign are rewritten through one
+// uniform-indexed register access per block.
 //
 // int16 Q (ascent_general): lane l owns columns 1024 b + 16 l + t, keeps
 // g_i = q_ii + 2 sum_{j != i} q_ij x_j (Delta_i = s_i g_i), and compares
@@ -134,11 +136,12 @@ __device__ inline int32_t wave_max_i32(int32_t v)
     return __builtin_amdgcn_readlane(v, 63);
 }
 
-// Column ownership of the int8 ascent: lane l owns [l PL, (l+1) PL), PL = 16 NB.
-// (Measured against lane l owning 1024 b + 16 l + t, which makes each 16-byte
-// row load of a wave one contiguous KB but needs a DPP min for the tie-break: the
-// contiguous ranges were 3% faster.)
-template <int NB> __device__ inline int asc_col0(int lane, int b) { return lane * 16 * NB + 16 * b; }
+// Column ownership of the int8 ascent: lane l owns 1024 b + 16 l + t.  The block
+// sits in the key above t, so the lowest column attaining the largest Delta is the
+// lowest (block, lane, t) and needs no reduction beyond the wave maximum.
+template <int NB> __device__ inline int asc_col0(int lane, int b) { return 1024 * b + 16 * lane; }
+// The key's tie-break part of column 1024 b + 16 l + t (bits 1..7).
+__device__ inline int32_t asc_tie(int b, int t) { return 32 * (7 - b) + 2 * (15 - t); }
 
 template <int NB>
 __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
@@ -149,9 +152,8 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         return;
     }
     uint64_t *xr = a.X + c * a.W;
-    // key_i = Delta_i * 256 + 2 L_i + x_i,  L_i = 127 - local_i (local = 16 b + t):
-    // the largest key is the largest Delta, then the lowest local index (the
-    // lowest column of the lane); bit 0 carries x_i.
+    // key_i = Delta_i * 256 + 32 (7 - b) + 2 (15 - t) + x_i: the largest key is the
+    // largest Delta, then the lowest block, then the lowest t; bit 0 carries x_i.
     v16i kk[NB];
     // s_i = 1 - 2 x_i as signed bytes, four per register
     uint32_t ss[NB][4];
@@ -171,7 +173,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 const int t = 4 * t4 + k;
-                const int32_t key = in ? kv[k] : 2 * (127 - (16 * b + t));
+                const int32_t key = in ? kv[k] : asc_tie(b, t);
                 kk[b][t] = key;
                 sw |= ((key & 1) ? 0xFFu : 0x01u) << (8 * k);
             }
@@ -190,24 +192,25 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
     __builtin_amdgcn_s_waitcnt(WAIT_VM_LGKM_0);
     for (;;) {
         const int32_t best = lane_max<NB>(kk);
-        const int32_t ld = best >> 8;
+        const int32_t ld = best >> 5;           // Delta * 8 + 7 - block
         V = wave_max_i32(ld);
-        if (V <= 0 || flips >= cap) break;
-        // the lowest lane attaining V holds the lowest column (lanes own ordered ranges)
+        if ((V >> 3) <= 0 || flips >= cap) break;
+        // among the lanes holding the largest Delta in the lowest block, the lowest
+        // lane holds the lowest column
         const int lstar = __ffsll((unsigned long long)__ballot(ld == V)) - 1;
         const int32_t bk = __builtin_amdgcn_readlane(best, lstar);
-        const int local = 127 - ((bk >> 1) & 127);
+        const int bs = 7 - ((bk >> 5) & 7), ts = 15 - ((bk >> 1) & 15);
         const int32_t xk = bk & 1;              // x_k before the flip
-        const int K = asc_col0<NB>(lstar, local >> 4) + (local & 15);
+        const int K = asc_col0<NB>(lstar, bs) + ts;
         // row k is read first: its latency is the flip's critical path
         const int8_t *row = qa + (int64_t)K * a.ncol_a;
         uint4 w[NB];
 #pragma unroll
         for (int b = 0; b < NB; b++) w[b] = ubqp_ldg16(row + asc_col0<NB>(lane, b));
-        const int bs = local >> 4, ts = local & 15;
-        // the flipped variable: Delta_k -> -V, x_k and s_k toggle (lane lstar only)
+        const int32_t dk = V >> 3;              // Delta_k
+        // the flipped variable: Delta_k -> -Delta_k, x_k and s_k toggle (lane lstar only)
         const bool own = lane == lstar;
-        const int32_t knew = -V * 256 + (bk & 0xFE) + (1 - xk);
+        const int32_t knew = -dk * 256 + (bk & 0xFE) + (1 - xk);
         const uint32_t sflip = own ? 0xFEu << (8 * (ts & 3)) : 0u;  // +1 <-> -1 as a byte
 #pragma unroll
         for (int b = 0; b < NB; b++) {
@@ -218,7 +221,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
                 for (int r = 0; r < 4; r++) ss[b][r] ^= (r == (ts >> 2)) ? sflip : 0u;
             }
         }
-        gain += V;
+        gain += dk;
         flips++;
         // Delta_i += 2 d s_i q_ik for i != k, with d = 1 - 2 x_k: key_i += (q_ik s_i) * 512 d
         const int32_t step = xk ? -512 : 512;
@@ -239,7 +242,7 @@ __device__ void ascend_i8(const AscArgs &a, int64_t p, int lane)
         }
         __builtin_amdgcn_s_setprio(0);
     }
-    if (V > 0 && a.max_flips == 0 && lane == 0) atomicOr(a.err, 1);  // safety cap reached
+    if ((V >> 3) > 0 && a.max_flips == 0 && lane == 0) atomicOr(a.err, 1);  // safety cap reached
 
 #pragma unroll
     for (int b = 0; b < NB; b++) {

@@ -446,11 +446,15 @@ __device__ void eval_body(const EvalArgs &a, int64_t tile)
         }
     } else if constexpr (EPI == EPI_KEYS) {
         // Ascent keys of the single-plane problem: with y = (x Q)_j and s = 1 - 2 x_j,
-        // Delta_j = q_jj + 2 s y_j, key_j = Delta_j * 256 + 2 (127 - j mod PL) + x_j.
-        // the key's tie-break part 2 (127 - local index in the ascent lane) per column
+        // Delta_j = q_jj + 2 s y_j, key_j = Delta_j * 256 + 32 (7 - j / 1024) +
+        // 2 (15 - j mod 16) + x_j (the ascent lane's block of 1024 columns above the
+        // column's place in its 16).
         int32_t tb[FN];
 #pragma unroll
-        for (int ni = 0; ni < FN; ni++) tb[ni] = 2 * (127 - (c0 + ni * 32 + r32) % a.keys_pl);
+        for (int ni = 0; ni < FN; ni++) {
+            const int col = c0 + ni * 32 + r32;
+            tb[ni] = 32 * (7 - (col >> 10)) + 2 * (15 - (col & 15));
+        }
 #pragma unroll
         for (int mi = 0; mi < FM; mi++) {
 #pragma unroll
@@ -585,7 +589,6 @@ EvalArgs ubqp_yrows_args(const ubqp_problem *p, const uint64_t *X, int64_t x_row
     a.offset = offset;
     a.Y = Y;
     a.diag = p->diag;
-    a.keys_pl = p->ncol_a / 64;
     a.n_tiles = (p->n_pad + YROWS_BN - 1) / YROWS_BN;
     return a;
 }

@@ -202,7 +202,6 @@ struct EvalArgs {            // int8 matrix-core contraction Y = X Q and its epi
     int64_t weight0;         // weight of plane 0 in the row dot
     int32_t m_tiles, n_tiles;
     const int32_t *diag;     // keys: q_jj
-    int32_t keys_pl;         // keys: columns per lane of the ascent (16 NB)
     int64_t bias;            // eval_init: f starts at bias * popcount(x)^2
     int32_t order;           // tile order: 0 n-tile-major, 1 m-tile-major (an eval variant choice)
     int32_t split_target;    // Y / key epilogues: split K below this many workgroups (0: never)
