@@ -22,9 +22,10 @@
 // its key.  The flipped variable's key and sign are rewritten through one
 // uniform-indexed register access per block.
 //
-// int16 Q (ascent_general): lane l owns columns 1024 b + 16 l + t, keeps
-// g_i = q_ii + 2 sum_{j != i} q_ij x_j (Delta_i = s_i g_i), and compares
-// (Delta, column) pairs across the wave.
+// int16 Q (ascend_i16): lane l owns the contiguous columns [l PL, (l+1) PL),
+// PL = 16 NB, keeps Delta_i itself (|Delta_i| < 2^30 leaves no room for a column
+// in 32 bits) and s_i as a byte, and finds the lowest column attaining the largest
+// Delta by the lowest lane, then that lane's lowest block and column.
 //
 // The starting deltas come from Y = X Q on the passers (the matrix-core kernel):
 //     y_i = w0 Y0_i + Y1_i + bias * popcount(x)   (bias / Y1 only when split)
